@@ -1,0 +1,238 @@
+/*
+ * idq.h -- C ABI of the i-DEQ inertial fixed-point solver for AMD MI355X (gfx950).
+ *
+ * The library solves imaging inverse problems y = A(x) + n by minimising
+ *     F(x) = f(x, y) + lambda * g(x)                         (paper, eq. inv_prob)
+ * with f(x, y) = 1/2 ||A(x) - y||^2 and the learned gradient-step potential
+ *     g(x) = 1/2 ||x - N_theta(x)||^2                        (paper, Sec. 2.2, eq. GS)
+ * where N_theta is a stack of zero-padded 3x3 conv layers with SoftPlus
+ * activations.  The solver is the i-DEQ iteration (eq. ideq, Alg. 1):
+ *     z^k     = x^k + beta (x^k - x^{k-1})                    (eq. Momentum, beta = 1 - alpha)
+ *     x^{k+1} = z^k - tau (grad f(z^k, y) + lambda grad g(z^k))
+ * with the adaptive restart of eq. restart and the per-image stopping rule
+ * ||x^{k+1} - x^k|| / ||x^k|| < tol of App. D.1.3.
+ *
+ * Conventions shared by every call
+ *   - Image tensors are dense, contiguous NCHW arrays (n images, c channels,
+ *     h rows, w columns) in DEVICE memory owned by the caller; element type is
+ *     given by `dtype` (IDQ_F64 = double, IDQ_F32 = float).  The library never
+ *     frees or keeps caller pointers beyond the call.
+ *   - If the network's input channel count is 1 and c > 1, N_theta is applied
+ *     to every channel as a separate grey image; otherwise c must equal it.
+ *   - Host arrays are marked "host"; everything else is a device pointer.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All calls are
+ *     asynchronous on `stream` unless stated otherwise.
+ *   - A context is not thread safe; use one per host thread.
+ *   - Every call returns IDQ_OK (0), a positive warning or a negative error;
+ *     idq_last_error() returns a thread-local message for the last failure.
+ *     No C++ exception crosses this interface.
+ */
+#ifndef IDQ_H
+#define IDQ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define IDQ_OK              0
+#define IDQ_W_MAXITER       1   /* some image hit max_iter; results written   */
+#define IDQ_E_INVAL        -1   /* null pointer, bad shape, dtype or option    */
+#define IDQ_E_NOMEM        -2   /* device allocation failed                    */
+#define IDQ_E_HIP          -3   /* HIP runtime error (message has the reason)  */
+#define IDQ_E_NONFINITE    -4   /* a non-finite iterate was produced           */
+#define IDQ_E_UNSUPPORTED  -5   /* option combination not implemented          */
+
+/* ---- element / arithmetic types ---------------------------------------- */
+#define IDQ_F64   0
+#define IDQ_F32   1
+#define IDQ_BF16  2   /* conv arithmetic only: bf16 operands, fp32 accumulate */
+
+/* ---- activations, operators, options ------------------------------------ */
+#define IDQ_ACT_SOFTPLUS   0
+#define IDQ_ACT_IDENTITY   1
+
+#define IDQ_OP_IDENTITY    0   /* A(x) = x                                     */
+#define IDQ_OP_BLUR_CIRC   1   /* A x = k (*) x, circular cross-correlation     */
+#define IDQ_OP_TANH_BLUR   2   /* A(x) = tanh(gain * (k (*) x)) / tanh(gain)    */
+
+#define IDQ_GRAD_AT_EXTRAPOLATED 0   /* gradient at z^k (Alg. 1)             */
+#define IDQ_GRAD_AT_CURRENT      1   /* gradient at x^k (heavy-ball form)    */
+
+#define IDQ_INIT_Y          0
+#define IDQ_INIT_ZERO       1
+#define IDQ_INIT_WARMSTART  2
+
+#define IDQ_MAX_LAYERS 8
+
+/* per-image status in idq_solve_info.status */
+#define IDQ_ST_CONVERGED   0
+#define IDQ_ST_MAXITER     1
+#define IDQ_ST_FIXED       2
+#define IDQ_ST_NONFINITE  -4
+
+typedef struct idq_ctx idq_ctx;
+typedef struct idq_ws idq_ws;
+
+/* Regularizer network N_theta (paper, Sec. 2.2 eq. GS; SoftPlus as in Sec. 3.3).
+ * channels[0..n_layers]: channels[0] == channels[n_layers] (N maps images to images).
+ * params (host, float64): packed [W_1, b_1, W_2, b_2, ...] with W_l in C order
+ * (c_out, c_in, 3, 3) and b_l (c_out).  The activation follows every layer but
+ * the last.  Copied at create time. */
+typedef struct {
+    int n_layers;                      /* 1..IDQ_MAX_LAYERS                     */
+    int channels[IDQ_MAX_LAYERS + 1];
+    int act;                           /* IDQ_ACT_*                             */
+    const double* params;              /* host                                  */
+} idq_net_desc;
+
+/* Forward operator A (paper, eq. inv_prob; the blur operators are the
+ * deblurring and nonlinear workloads).  taps (host, float64): kh x kw row-major,
+ * kh and kw odd, centred; the correlation is
+ *   (B x)[i,j] = sum_{a,b} k[a,b] x[(i+a-(kh-1)/2) mod h, (j+b-(kw-1)/2) mod w]. */
+typedef struct {
+    int kind;                          /* IDQ_OP_*                              */
+    int kh, kw;                        /* taps size (ignored for identity)      */
+    const double* taps;                /* host, copied at create time           */
+    double gain;                       /* tanh-blur gamma (e.g. 2.0)            */
+} idq_op_desc;
+
+/* Options of idq_solve.  Fill with idq_solve_opts_default() first. */
+typedef struct {
+    double beta;            /* inertia beta = 1 - alpha (eq. Momentum)          */
+    double tau;             /* step size; 0 => 0.9 / L by power iteration        */
+    double lambda;          /* regularisation weight                             */
+    double tol;             /* stopping tolerance on the relative residual       */
+    int    max_iter;        /* per-image iteration cap                           */
+    int    fixed_iters;     /* > 0: exactly this many updates, tol ignored       */
+    double restart_B;       /* restart threshold B (eq. restart); <= 0 => off    */
+    int    grad_at;         /* IDQ_GRAD_AT_*                                     */
+    int    conv_prec;       /* IDQ_F64 (dtype F64 only) | IDQ_F32 | IDQ_BF16      */
+    double switch_tol;      /* BF16 phase ends when rel < switch_tol ...          */
+    int    switch_patience; /* ... or after this many BF16 steps with no new best */
+    int    power_iters;     /* power iterations when tau == 0                    */
+    const void* power_v0;   /* device, shape of y: power-iteration start vector  */
+    int    poll_every;      /* iterations enqueued between host polls            */
+    int    init;            /* IDQ_INIT_* used when x0 == NULL                    */
+    idq_ws* ws;             /* warm-start network for IDQ_INIT_WARMSTART          */
+    int    ws_prec;         /* IDQ_F32 | IDQ_BF16 for the warm-start inference    */
+    int    use_graph;       /* 1: replay captured HIP graphs of the iteration     */
+} idq_solve_opts;
+
+/* Per-image results of idq_solve (host array of n entries). */
+typedef struct {
+    int    iters;           /* updates performed                                  */
+    int    iters_low;       /* of which in the BF16 phase                          */
+    int    restarts;        /* restarts fired                                      */
+    int    status;          /* IDQ_ST_*                                            */
+    double rel;             /* last relative residual ||x^{k+1}-x^k|| / ||x^k||    */
+    double tau;             /* step size used                                      */
+} idq_solve_info;
+
+#define IDQ_BWD_JFB       0   /* Jacobian-free backprop: adjoint u = v           */
+#define IDQ_BWD_IMPLICIT  1   /* adjoint fixed point u = (I - tau H) u + v        */
+
+typedef struct {
+    int    mode;              /* IDQ_BWD_*                                       */
+    double tau, lambda;       /* the forward pass's step size and weight          */
+    int    adjoint_max_iter;
+    double adjoint_tol;       /* on ||u_{j+1} - u_j|| / ||u_j|| (batch norms)     */
+    double adjoint_beta;      /* inertia applied to the adjoint iteration          */
+} idq_bwd_opts;
+
+typedef struct {
+    int    adjoint_iters;
+    double adjoint_rel;
+} idq_bwd_info;
+
+/* ---- library ------------------------------------------------------------- */
+const char* idq_last_error(void);          /* thread-local message, never NULL  */
+int idq_version(void);                     /* 10000*major + 100*minor + patch   */
+void idq_solve_opts_default(idq_solve_opts* o);  /* host; beta .5, lambda 1, tol
+                                              1e-4, max_iter 1000, F32, ...       */
+
+/* Create a context on HIP device `device`: copies the network and operator,
+ * packs the weights for every conv arithmetic.  Synchronous. */
+int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, int device);
+/* Destroy a context and free its device memory.  Synchronous. */
+int idq_destroy(idq_ctx* ctx);
+/* Replace the network parameters (host float64, packed as in idq_net_desc);
+ * `count` must equal the packed size.  Synchronous. */
+int idq_set_params(idq_ctx* ctx, const double* params, long long count);
+/* Number of packed network parameters. */
+long long idq_num_params(const idq_ctx* ctx);
+
+/* Ax = A(x) (eq. inv_prob).  x, Ax: n*c*h*w of dtype. */
+int idq_apply_A(idq_ctx* ctx, const void* x, void* Ax, int n, int c, int h, int w,
+                int dtype, void* stream);
+/* out = J_A(x)^T v, the adjoint (transposed Jacobian) of A at x; x may be NULL
+ * for the linear operators.  This is the operator of grad f = J_A^T (A x - y). */
+int idq_apply_AT(idq_ctx* ctx, const void* x, const void* v, void* out,
+                 int n, int c, int h, int w, int dtype, void* stream);
+/* grad = grad_x f(x, y) = J_A(x)^T (A(x) - y). */
+int idq_grad_data(idq_ctx* ctx, const void* x, const void* y, void* grad,
+                  int n, int c, int h, int w, int dtype, void* stream);
+/* grad = grad g(x) = r - J_N(x)^T r, r = x - N(x) (derivative of eq. GS).
+ * g_val (host, nullable): n per-image values of g; when given the call is
+ * synchronous.  conv_prec: IDQ_F64 (dtype F64) | IDQ_F32 | IDQ_BF16. */
+int idq_grad_reg(idq_ctx* ctx, const void* x, void* grad, double* g_val,
+                 int n, int c, int h, int w, int dtype, int conv_prec, void* stream);
+/* out = H v with H = Hessian of g at x (which = 0) or of F at (x, y) with the
+ * given lambda (which = 1; y may be NULL for which = 0). */
+int idq_hvp(idq_ctx* ctx, const void* x, const void* y, const void* v, void* out,
+            double lambda, int which, int n, int c, int h, int w, int dtype,
+            int conv_prec, void* stream);
+/* L = largest-magnitude eigenvalue of the batch Hessian of F at (x, y) by
+ * `iters` steps of v <- Hv/||Hv|| from v0 (device, same shape), L = <v, Hv>.
+ * Norms and dots in float64.  L (host) is written; synchronous. */
+int idq_lipschitz(idq_ctx* ctx, const void* x, const void* y, const void* v0,
+                  double lambda, int iters, int n, int c, int h, int w, int dtype,
+                  int conv_prec, double* L);
+/* The i-DEQ forward pass (Alg. 1) on a batch of n independent images.
+ * y: measurements; x0: initial iterate or NULL (then opts->init); x_out: the
+ * returned iterate of every image (the first iterate meeting the stopping
+ * rule, or the last one).  info: host array of n entries.  Synchronous: it
+ * returns after every image stopped.  Returns IDQ_OK, IDQ_W_MAXITER if some
+ * image hit max_iter, or IDQ_E_NONFINITE if some image produced a non-finite
+ * iterate (its status says which; other images are still valid). */
+int idq_solve(idq_ctx* ctx, const void* y, const void* x0, void* x_out,
+              int n, int c, int h, int w, int dtype, const idq_solve_opts* opts,
+              idq_solve_info* info, void* stream);
+/* Gradient of a loss through the fixed point xbar (paper, App. D.1):
+ * dl_dx = dloss/dxbar (device, image shaped).  Writes dtheta (device, dtype,
+ * packed like the network parameters) and *dlambda (host).  IMPLICIT solves
+ * u = (I - tau H_F(xbar)) u + v by fixed-point iteration; JFB uses u = v.
+ * dtheta = -tau lambda d/dtheta <u, grad g(xbar)>, dlambda = -tau <grad g, u>.
+ * Synchronous. */
+int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_dx,
+                 void* dtheta, double* dlambda, int n, int c, int h, int w, int dtype,
+                 const idq_bwd_opts* opts, idq_bwd_info* info, void* stream);
+
+/* ---- learned warm start x0 = y + W_phi(y) ---------------------------------
+ * 2-level encoder-decoder on 3-channel images (h, w even):
+ *   3->32->32 | avgpool 2x2 | 32->64->64->64->64 | nearest upsample |
+ *   concat(upsampled 64, skip 32) | 96->32->32->3, SoftPlus after all but the last.
+ * params (host, float64): the 9 convs packed like idq_net_desc.params. */
+int idq_ws_create(idq_ws** out, const double* params, long long count, int device);
+int idq_ws_destroy(idq_ws* ws);
+long long idq_ws_num_params(void);
+int idq_ws_get_params(idq_ws* ws, double* params);          /* host out; sync  */
+int idq_ws_set_params(idq_ws* ws, const double* params);    /* host in; sync   */
+/* x0 = y + W_phi(y); y, x0: float32 NCHW with c == 3.  prec: F32 | BF16. */
+int idq_ws_forward(idq_ws* ws, const void* y, void* x0, int n, int c, int h, int w,
+                   int prec, void* stream);
+/* One Adam step (lr, betas 0.9/0.999, eps 1e-8) on the mean squared error
+ * between y + W_phi(y) and target (float32 NCHW).  Master weights float32;
+ * prec selects the conv arithmetic.  loss (host, nullable) receives the loss
+ * before the step; synchronous when loss != NULL. */
+int idq_ws_train_step(idq_ws* ws, const void* y, const void* target, int n, int c,
+                      int h, int w, int prec, double lr, double* loss, void* stream);
+/* Gradient of the same loss w.r.t. the parameters without updating them:
+ * grad (device, float32, packed like params).  loss as above. */
+int idq_ws_grad(idq_ws* ws, const void* y, const void* target, void* grad, int n,
+                int c, int h, int w, int prec, double* loss, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IDQ_H */

@@ -1,0 +1,254 @@
+"""Python binding of the i-DEQ HIP library with the C ABI's names.
+
+PyTorch supplies device memory and streams only; every step of the method runs
+in the library's kernels.  Tensors are CUDA (HIP) tensors, contiguous NCHW,
+float64 or float32.
+
+    ctx = IDQ(layers, op_kind="blur", taps=k)      # layers: list of (W, b) arrays
+    x, info = ctx.solve(y, beta=0.5, lam=1.0, tau=0.0, power_v0=v0, conv_prec="bf16")
+"""
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"f64": L.IDQ_F64, "f32": L.IDQ_F32, "bf16": L.IDQ_BF16,
+         L.IDQ_F64: L.IDQ_F64, L.IDQ_F32: L.IDQ_F32, L.IDQ_BF16: L.IDQ_BF16}
+_OPS = {"identity": L.IDQ_OP_IDENTITY, "blur": L.IDQ_OP_BLUR_CIRC, "tanh_blur": L.IDQ_OP_TANH_BLUR}
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return L.IDQ_F64
+    if t.dtype == torch.float32:
+        return L.IDQ_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _shape4(t):
+    if t.dim() != 4:
+        raise ValueError("expected an (n, c, h, w) tensor")
+    return tuple(int(s) for s in t.shape)
+
+
+def pack_layers(layers):
+    """Flat float64 [W_1, b_1, W_2, b_2, ...] from a list of (W, b)."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float64).ravel(),
+                                           np.asarray(b, np.float64).ravel()])
+                           for W, b in layers])
+
+
+@dataclass
+class SolveResult:
+    iters: np.ndarray
+    iters_low: np.ndarray
+    restarts: np.ndarray
+    status: np.ndarray
+    rel: np.ndarray
+    tau: float
+    code: int
+
+
+class IDQ:
+    """One library context: regularizer network + forward operator on a device."""
+
+    def __init__(self, layers=None, act="softplus", op_kind="identity", taps=None, gain=2.0,
+                 device=0):
+        lib = L.lib()
+        self.layers = [(np.asarray(W, np.float64), np.asarray(b, np.float64))
+                       for W, b in (layers or [])]
+        nd = L.NetDesc()
+        self._params = None
+        if self.layers:
+            chans = [self.layers[0][0].shape[1]] + [W.shape[0] for W, _ in self.layers]
+            nd.n_layers = len(self.layers)
+            for i, cch in enumerate(chans):
+                nd.channels[i] = cch
+            nd.act = L.IDQ_ACT_SOFTPLUS if act == "softplus" else L.IDQ_ACT_IDENTITY
+            self._params = np.ascontiguousarray(pack_layers(self.layers))
+            nd.params = self._params.ctypes.data_as(C.POINTER(C.c_double))
+            self.channels = chans
+        else:
+            nd.n_layers = 0
+            self.channels = []
+        od = L.OpDesc()
+        od.kind = _OPS[op_kind]
+        self._taps = None
+        if op_kind != "identity":
+            self._taps = np.ascontiguousarray(np.asarray(taps, np.float64))
+            od.kh, od.kw = self._taps.shape
+            od.taps = self._taps.ctypes.data_as(C.POINTER(C.c_double))
+        od.gain = float(gain)
+        self.op_kind = op_kind
+        h = C.c_void_p()
+        L.check(lib.idq_create(C.byref(h), C.byref(nd) if self.layers else None, C.byref(od),
+                               int(device)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().idq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self):
+        return int(L.lib().idq_num_params(self._h))
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(np.asarray(flat, np.float64))
+        L.check(L.lib().idq_set_params(self._h, flat.ctypes.data_as(C.POINTER(C.c_double)),
+                                       flat.size))
+
+    # ---- operators -------------------------------------------------------------
+    def apply_A(self, x):
+        out = torch.empty_like(x)
+        L.check(L.lib().idq_apply_A(self._h, _ptr(x), _ptr(out), *_shape4(x), _dtype_code(x),
+                                    _stream()))
+        return out
+
+    def apply_AT(self, v, x=None):
+        out = torch.empty_like(v)
+        L.check(L.lib().idq_apply_AT(self._h, _ptr(x), _ptr(v), _ptr(out), *_shape4(v),
+                                     _dtype_code(v), _stream()))
+        return out
+
+    def grad_data(self, x, y):
+        out = torch.empty_like(x)
+        L.check(L.lib().idq_grad_data(self._h, _ptr(x), _ptr(y), _ptr(out), *_shape4(x),
+                                      _dtype_code(x), _stream()))
+        return out
+
+    def grad_reg(self, x, conv_prec=None, with_value=False):
+        prec = _PREC[conv_prec] if conv_prec is not None else _dtype_code(x)
+        out = torch.empty_like(x)
+        gv = np.zeros(x.shape[0]) if with_value else None
+        L.check(L.lib().idq_grad_reg(self._h, _ptr(x), _ptr(out),
+                                     gv.ctypes.data_as(C.POINTER(C.c_double)) if with_value else None,
+                                     *_shape4(x), _dtype_code(x), prec, _stream()))
+        return (out, gv) if with_value else out
+
+    def hvp(self, x, v, y=None, lam=1.0, which="reg", conv_prec=None):
+        prec = _PREC[conv_prec] if conv_prec is not None else _dtype_code(x)
+        out = torch.empty_like(x)
+        L.check(L.lib().idq_hvp(self._h, _ptr(x), _ptr(y), _ptr(v), _ptr(out), float(lam),
+                                0 if which == "reg" else 1, *_shape4(x), _dtype_code(x), prec,
+                                _stream()))
+        return out
+
+    def lipschitz(self, x, y, v0, lam=1.0, iters=30, conv_prec=None):
+        prec = _PREC[conv_prec] if conv_prec is not None else _dtype_code(x)
+        Lv = C.c_double(0.0)
+        torch.cuda.current_stream().synchronize()
+        L.check(L.lib().idq_lipschitz(self._h, _ptr(x), _ptr(y), _ptr(v0), float(lam), int(iters),
+                                      *_shape4(x), _dtype_code(x), prec, C.byref(Lv)))
+        return Lv.value
+
+    # ---- solver ------------------------------------------------------------------
+    def solve(self, y, x0=None, out=None, beta=0.5, tau=0.0, lam=1.0, tol=1e-4, max_iter=1000,
+              fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
+              switch_tol=1e-3, switch_patience=10, power_iters=30, power_v0=None,
+              poll_every=8, init="y", ws=None, ws_prec="bf16", use_graph=False):
+        o = L.SolveOpts()
+        L.lib().idq_solve_opts_default(C.byref(o))
+        o.beta, o.tau, o.lambda_, o.tol = float(beta), float(tau), float(lam), float(tol)
+        o.max_iter, o.fixed_iters = int(max_iter), int(fixed_iters)
+        o.restart_B = float(restart_B) if restart_B and np.isfinite(restart_B) else 0.0
+        o.grad_at = L.IDQ_GRAD_AT_CURRENT if grad_at == "current" else L.IDQ_GRAD_AT_EXTRAPOLATED
+        o.conv_prec = _PREC[conv_prec] if conv_prec is not None else _dtype_code(y)
+        o.switch_tol, o.switch_patience = float(switch_tol), int(switch_patience)
+        o.power_iters = int(power_iters)
+        o.power_v0 = _ptr(power_v0).value if power_v0 is not None else None
+        o.poll_every = int(poll_every)
+        o.init = {"y": L.IDQ_INIT_Y, "zero": L.IDQ_INIT_ZERO,
+                  "warmstart": L.IDQ_INIT_WARMSTART}[init]
+        o.ws = ws._h.value if ws is not None else None
+        o.ws_prec = _PREC[ws_prec]
+        o.use_graph = int(bool(use_graph))
+        n = y.shape[0]
+        info = (L.SolveInfo * n)()
+        x = out if out is not None else torch.empty_like(y)
+        code = L.lib().idq_solve(self._h, _ptr(y), _ptr(x0), _ptr(x), *_shape4(y), _dtype_code(y),
+                                 C.byref(o), info, _stream())
+        L.check(code, allow=(L.IDQ_OK, L.IDQ_W_MAXITER, L.IDQ_E_NONFINITE))
+        res = SolveResult(iters=np.array([i.iters for i in info]),
+                          iters_low=np.array([i.iters_low for i in info]),
+                          restarts=np.array([i.restarts for i in info]),
+                          status=np.array([i.status for i in info]),
+                          rel=np.array([i.rel for i in info]),
+                          tau=float(info[0].tau), code=code)
+        return x, res
+
+    def backward(self, xbar, y, dl_dx, tau, lam, mode="implicit", adjoint_max_iter=500,
+                 adjoint_tol=1e-6, adjoint_beta=0.0):
+        o = L.BwdOpts()
+        o.mode = L.IDQ_BWD_IMPLICIT if mode == "implicit" else L.IDQ_BWD_JFB
+        o.tau, o.lambda_ = float(tau), float(lam)
+        o.adjoint_max_iter, o.adjoint_tol = int(adjoint_max_iter), float(adjoint_tol)
+        o.adjoint_beta = float(adjoint_beta)
+        dtheta = torch.empty(self.num_params, dtype=xbar.dtype, device=xbar.device)
+        dlam = C.c_double(0.0)
+        info = L.BwdInfo()
+        L.check(L.lib().idq_backward(self._h, _ptr(xbar), _ptr(y), _ptr(dl_dx), _ptr(dtheta),
+                                     C.byref(dlam), *_shape4(xbar), _dtype_code(xbar), C.byref(o),
+                                     C.byref(info), _stream()))
+        return dtheta, dlam.value, (info.adjoint_iters, info.adjoint_rel)
+
+
+class IDQSolve(torch.autograd.Function):
+    """x_bar = fixed point of the i-DEQ iteration; gradients by the implicit
+    (or JFB) backward of the library.
+
+    Usage: IDQSolve.apply(y, theta, lam, ctx, solve_kwargs, bwd_kwargs) with
+    theta the flat network parameters (float64 CPU tensor, loaded into the
+    context before the solve) and lam a 0-d tensor.
+    """
+
+    @staticmethod
+    def forward(fctx, y, theta, lam, ctx, solve_kwargs, bwd_kwargs):
+        ctx.set_params(theta.detach().cpu().double().numpy())
+        kw = dict(solve_kwargs)
+        kw["lam"] = float(lam)
+        x, res = ctx.solve(y, **kw)
+        fctx.save_for_backward(x, y)
+        fctx.idq = ctx
+        fctx.tau = res.tau
+        fctx.lam = float(lam)
+        fctx.bwd_kwargs = bwd_kwargs
+        fctx.theta_meta = (theta.dtype, theta.device)
+        fctx.lam_meta = (lam.dtype, lam.device)
+        fctx.res = res
+        return x
+
+    @staticmethod
+    def backward(fctx, grad_x):
+        x, y = fctx.saved_tensors
+        dtheta, dlam, _ = fctx.idq.backward(x, y, grad_x.contiguous(), fctx.tau, fctx.lam,
+                                            **fctx.bwd_kwargs)
+        tdt, tdev = fctx.theta_meta
+        ldt, ldev = fctx.lam_meta
+        return (None, dtheta.to(device=tdev, dtype=tdt),
+                torch.tensor(dlam, dtype=ldt, device=ldev), None, None, None)

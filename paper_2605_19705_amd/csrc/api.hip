@@ -1,0 +1,1049 @@
+// C ABI of the i-DEQ library: context management, operator and regularizer
+// calls, the inertial fixed-point solver (Alg. 1), the power iteration for the
+// step size and the implicit / JFB backward pass (App. D.1).
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+namespace idq {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int Workspace::get(int slot, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  if (cap[slot] < bytes) {
+    if (ptr[slot]) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return fail(IDQ_E_HIP, std::string("sync: ") + hipGetErrorString(e));
+      hipFree(ptr[slot]);
+      ptr[slot] = nullptr;
+      cap[slot] = 0;
+    }
+    size_t want = (bytes + 255) / 256 * 256;
+    if (hipMalloc(&ptr[slot], want) != hipSuccess) {
+      ptr[slot] = nullptr;
+      return fail(IDQ_E_NOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    cap[slot] = want;
+  }
+  *out = ptr[slot];
+  return IDQ_OK;
+}
+
+void Workspace::release() {
+  for (int i = 0; i < W_NSLOTS; ++i) {
+    if (ptr[i]) hipFree(ptr[i]);
+    ptr[i] = nullptr;
+    cap[i] = 0;
+  }
+}
+
+namespace {
+
+size_t math_size(int prec) { return prec == PREC_F64 ? 8 : 4; }
+size_t act_size(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
+
+int upload(void** dst, const void* src, size_t bytes) {
+  IDQ_HIP(hipMalloc(dst, bytes));
+  IDQ_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return IDQ_OK;
+}
+
+void free_layers(idq_ctx* ctx) {
+  for (auto& L : ctx->layers)
+    for (int p = 0; p < 3; ++p) {
+      void** all[] = {&L.fwd[p], &L.tr[p], &L.bias[p], &L.fwd_mfma[p], &L.tr_mfma[p]};
+      for (void** q : all)
+        if (*q) {
+          hipFree(*q);
+          *q = nullptr;
+        }
+    }
+}
+
+// Pack every layer's weights for every arithmetic from ctx->params.
+int pack_weights(idq_ctx* ctx) {
+  free_layers(ctx);
+  ctx->layers.assign(ctx->L, LayerW());
+  size_t off = 0;
+  for (int l = 0; l < ctx->L; ++l) {
+    LayerW& lw = ctx->layers[l];
+    const int ci = ctx->ch[l], co = ctx->ch[l + 1];
+    lw.ci = ci;
+    lw.co = co;
+    const double* W = ctx->params.data() + off;
+    const double* b = W + static_cast<size_t>(co) * ci * 9;
+    off += static_cast<size_t>(co) * ci * 9 + co;
+    // transposed-conv weights: Wt[c][o][t] = W[o][c][8 - t]
+    std::vector<double> Wt(static_cast<size_t>(co) * ci * 9);
+    for (int o = 0; o < co; ++o)
+      for (int c = 0; c < ci; ++c)
+        for (int t = 0; t < 9; ++t)
+          Wt[(static_cast<size_t>(c) * co + o) * 9 + t] = W[(static_cast<size_t>(o) * ci + c) * 9 + 8 - t];
+    const size_t nw = static_cast<size_t>(co) * ci * 9;
+    IDQ_TRY(upload(&lw.fwd[PREC_F64], W, nw * 8));
+    IDQ_TRY(upload(&lw.tr[PREC_F64], Wt.data(), nw * 8));
+    IDQ_TRY(upload(&lw.bias[PREC_F64], b, co * 8));
+    for (int prec : {PREC_F32, PREC_BF16}) {
+      std::vector<float> f(nw), ft(nw), fb(co);
+      for (size_t i = 0; i < nw; ++i) {
+        f[i] = static_cast<float>(W[i]);
+        ft[i] = static_cast<float>(Wt[i]);
+        if (prec == PREC_BF16) {
+          f[i] = round_bf(f[i]);
+          ft[i] = round_bf(ft[i]);
+        }
+      }
+      for (int o = 0; o < co; ++o) fb[o] = static_cast<float>(b[o]);
+      IDQ_TRY(upload(&lw.fwd[prec], f.data(), nw * 4));
+      IDQ_TRY(upload(&lw.tr[prec], ft.data(), nw * 4));
+      IDQ_TRY(upload(&lw.bias[prec], fb.data(), co * 4));
+      if (mfma_supported(prec, ci, co)) {
+        std::vector<char> buf(pack_mfma_weights(prec, ci, co, W, nullptr));
+        pack_mfma_weights(prec, ci, co, W, buf.data());
+        IDQ_TRY(upload(&lw.fwd_mfma[prec], buf.data(), buf.size()));
+      }
+      if (mfma_supported(prec, co, ci)) {
+        std::vector<char> buf(pack_mfma_weights(prec, co, ci, Wt.data(), nullptr));
+        pack_mfma_weights(prec, co, ci, Wt.data(), buf.data());
+        IDQ_TRY(upload(&lw.tr_mfma[prec], buf.data(), buf.size()));
+      }
+    }
+  }
+  return IDQ_OK;
+}
+
+int check_shape(const idq_ctx* ctx, int n, int c, int h, int w, Geometry* g) {
+  if (n <= 0 || c <= 0 || h <= 0 || w <= 0) return fail(IDQ_E_INVAL, "non-positive shape");
+  g->n = n;
+  g->c = c;
+  g->h = h;
+  g->w = w;
+  g->per = static_cast<long long>(c) * h * w;
+  if (ctx->L > 0) {
+    const int c0 = ctx->ch[0];
+    if (c == c0) {
+      g->NI = n;
+      g->img_div = 1;
+    } else if (c0 == 1) {
+      g->NI = n * c;
+      g->img_div = c;
+    } else {
+      return fail(IDQ_E_INVAL, "image channels " + std::to_string(c) + " do not match the network's " +
+                                   std::to_string(c0));
+    }
+  } else {
+    g->NI = n;
+    g->img_div = 1;
+  }
+  return IDQ_OK;
+}
+
+int check_prec(int dtype, int prec) {
+  if (dtype != IDQ_F64 && dtype != IDQ_F32) return fail(IDQ_E_INVAL, "dtype must be IDQ_F64 or IDQ_F32");
+  if (dtype == IDQ_F64 && prec != IDQ_F64)
+    return fail(IDQ_E_INVAL, "float64 tensors need float64 conv arithmetic");
+  if (dtype == IDQ_F32 && prec != IDQ_F32 && prec != IDQ_BF16)
+    return fail(IDQ_E_INVAL, "float32 tensors need F32 or BF16 conv arithmetic");
+  return IDQ_OK;
+}
+
+size_t max_ch(const idq_ctx* ctx) {
+  int m = 1;
+  for (int l = 0; l <= ctx->L; ++l) m = std::max(m, ctx->ch[l]);
+  return static_cast<size_t>(m);
+}
+
+ConvArgs conv_base(const idq_ctx* ctx, const Geometry& g, int l, bool transposed, int prec,
+                   const int* gate, int mask) {
+  ConvArgs a{};
+  const LayerW& lw = ctx->layers[l];
+  a.NI = g.NI;
+  a.H = g.h;
+  a.W = g.w;
+  a.CI = transposed ? lw.co : lw.ci;
+  a.CO = transposed ? lw.ci : lw.co;
+  a.act = ctx->act;
+  a.wgt = transposed ? lw.tr[prec] : lw.fwd[prec];
+  a.wmfma = transposed ? lw.tr_mfma[prec] : lw.fwd_mfma[prec];
+  a.bias = transposed ? nullptr : lw.bias[prec];
+  a.gate = gate;
+  a.gate_mask = mask;
+  a.img_div = g.img_div;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Regularizer passes
+// ---------------------------------------------------------------------------
+
+// Forward pass of N at p (state tensor): stores h_1..h_{L-1} and r = p - N(p).
+int net_forward(idq_ctx* ctx, const Geometry& g, int prec, const void* p, void* r,
+                const int* gate, int mask, hipStream_t s) {
+  const int L = ctx->L;
+  const size_t abytes = static_cast<size_t>(g.pix()) * max_ch(ctx) * act_size(prec);
+  const void* prev = p;
+  for (int l = 0; l < L; ++l) {
+    ConvArgs a = conv_base(ctx, g, l, false, prec, gate, mask);
+    a.in0 = prev;
+    a.in_fmt = l == 0 ? F_NCHW : F_NHWC;
+    a.pro = l == 0 ? P_NONE : P_ACT;
+    if (l == L - 1) {
+      a.out_fmt = F_NCHW;
+      a.epi = E_RES;
+      a.e0 = p;
+      a.out0 = r;
+    } else {
+      void* h;
+      IDQ_TRY(ctx->ws.get(W_H0 + l, abytes, &h));
+      a.out_fmt = F_NHWC;
+      a.epi = E_STORE;
+      a.out0 = h;
+      prev = h;
+    }
+    IDQ_TRY(launch_conv(a, prec, s));
+  }
+  return IDQ_OK;
+}
+
+// grad g(p) = r - J_N(p)^T r into q (state tensor); uses the buffers of net_forward.
+int net_grad(idq_ctx* ctx, const Geometry& g, int prec, const void* p, void* q,
+             const int* gate, int mask, hipStream_t s) {
+  const int L = ctx->L;
+  const size_t abytes = static_cast<size_t>(g.pix()) * max_ch(ctx) * act_size(prec);
+  const size_t sbytes = static_cast<size_t>(g.n) * g.per * math_size(prec);
+  void* r;
+  IDQ_TRY(ctx->ws.get(W_R, sbytes, &r));
+  IDQ_TRY(net_forward(ctx, g, prec, p, r, gate, mask, s));
+  void *d0, *d1;
+  IDQ_TRY(ctx->ws.get(W_TMP0, abytes, &d0));
+  IDQ_TRY(ctx->ws.get(W_TMP1, abytes, &d1));
+  const void* din = r;
+  for (int l = L - 1; l >= 0; --l) {
+    ConvArgs a = conv_base(ctx, g, l, true, prec, gate, mask);
+    a.in0 = din;
+    a.in_fmt = l == L - 1 ? F_NCHW : F_NHWC;
+    a.pro = P_NONE;
+    if (l == 0) {
+      a.out_fmt = F_NCHW;
+      a.epi = E_SUB;
+      a.e0 = r;
+      a.out0 = q;
+    } else {
+      void* h;
+      IDQ_TRY(ctx->ws.get(W_H0 + l - 1, abytes, &h));
+      void* o = (din == d0) ? d1 : d0;
+      a.out_fmt = F_NHWC;
+      a.epi = E_DELTA;
+      a.e0 = h;
+      a.out0 = o;
+      din = o;
+    }
+    IDQ_TRY(launch_conv(a, prec, s));
+  }
+  return IDQ_OK;
+}
+
+// Forward-over-reverse pass at x along w: Hw = H_g(x) w (state tensor).  Keeps
+// h_l, h'_l, delta_l, delta'_l (l < L), r and r' in their workspace slots.
+int net_hvp(idq_ctx* ctx, const Geometry& g, int prec, const void* x, const void* w, void* Hw,
+            hipStream_t s) {
+  const int L = ctx->L;
+  const size_t abytes = static_cast<size_t>(g.pix()) * max_ch(ctx) * act_size(prec);
+  const size_t sbytes = static_cast<size_t>(g.n) * g.per * math_size(prec);
+  void *r, *rd, *t;
+  IDQ_TRY(ctx->ws.get(W_R, sbytes, &r));
+  IDQ_TRY(ctx->ws.get(W_RD, sbytes, &rd));
+  IDQ_TRY(ctx->ws.get(W_T, abytes, &t));
+  IDQ_TRY(net_forward(ctx, g, prec, x, r, nullptr, 0, s));
+  // tangents
+  const void* prev_h = nullptr;
+  const void* prev_hd = w;
+  for (int l = 0; l < L; ++l) {
+    ConvArgs a = conv_base(ctx, g, l, false, prec, nullptr, 0);
+    a.bias = nullptr;
+    if (l == 0) {
+      a.in0 = w;
+      a.in_fmt = F_NCHW;
+      a.pro = P_NONE;
+    } else {
+      a.in0 = prev_h;
+      a.in1 = prev_hd;
+      a.in_fmt = F_NHWC;
+      a.pro = P_JVP;
+    }
+    if (l == L - 1) {
+      a.out_fmt = F_NCHW;
+      a.epi = E_SUB;
+      a.e0 = w;
+      a.out0 = rd;
+    } else {
+      void *h, *hd;
+      IDQ_TRY(ctx->ws.get(W_H0 + l, abytes, &h));
+      IDQ_TRY(ctx->ws.get(W_HD0 + l, abytes, &hd));
+      a.out_fmt = F_NHWC;
+      a.epi = E_RAW;
+      a.out0 = hd;
+      prev_h = h;
+      prev_hd = hd;
+    }
+    IDQ_TRY(launch_conv(a, prec, s));
+  }
+  // reverse pass for (delta, delta')
+  const void* din = r;
+  const void* ddin = rd;
+  for (int l = L - 1; l >= 0; --l) {
+    if (l == 0) {
+      ConvArgs a = conv_base(ctx, g, 0, true, prec, nullptr, 0);
+      a.in0 = ddin;
+      a.in_fmt = L == 1 ? F_NCHW : F_NHWC;
+      a.pro = P_NONE;
+      a.out_fmt = F_NCHW;
+      a.epi = E_SUB;
+      a.e0 = rd;
+      a.out0 = Hw;
+      IDQ_TRY(launch_conv(a, prec, s));
+      break;
+    }
+    void *h, *hd, *dl, *ddl;
+    IDQ_TRY(ctx->ws.get(W_H0 + l - 1, abytes, &h));
+    IDQ_TRY(ctx->ws.get(W_HD0 + l - 1, abytes, &hd));
+    IDQ_TRY(ctx->ws.get(W_DL0 + l - 1, abytes, &dl));
+    IDQ_TRY(ctx->ws.get(W_DDL0 + l - 1, abytes, &ddl));
+    ConvArgs a = conv_base(ctx, g, l, true, prec, nullptr, 0);
+    a.in0 = din;
+    a.in_fmt = l == L - 1 ? F_NCHW : F_NHWC;
+    a.pro = P_NONE;
+    a.out_fmt = F_NHWC;
+    a.epi = E_RAW;
+    a.out0 = t;
+    IDQ_TRY(launch_conv(a, prec, s));
+    ConvArgs b = a;
+    b.in0 = ddin;
+    b.epi = E_DDOT;
+    b.e0 = h;
+    b.e1 = hd;
+    b.e2 = t;
+    b.out0 = ddl;
+    b.out1 = dl;
+    IDQ_TRY(launch_conv(b, prec, s));
+    din = dl;
+    ddin = ddl;
+  }
+  return IDQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Forward operator passes
+// ---------------------------------------------------------------------------
+StencilArgs stencil_base(const idq_ctx* ctx, const Geometry& g, const int* gate) {
+  StencilArgs a{};
+  a.NP = g.n * g.c;
+  a.H = g.h;
+  a.W = g.w;
+  a.kh = ctx->kh;
+  a.kw = ctx->kw;
+  a.gain = ctx->gain;
+  a.gate = gate;
+  a.plane_div = g.c;
+  return a;
+}
+
+int copy_state(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  IDQ_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  return IDQ_OK;
+}
+
+// grad f(p, y) = J_A(p)^T (A(p) - y) into gf (not used for the identity,
+// whose gradient p - y the update kernel forms itself unless `force`).
+int data_grad(idq_ctx* ctx, const Geometry& g, int dtype, const void* p, const void* y, void* gf,
+              const int* gate, hipStream_t s, bool force) {
+  const size_t sbytes = static_cast<size_t>(g.n) * g.per * elem_size(dtype);
+  if (ctx->op_kind == IDQ_OP_IDENTITY) {
+    if (force) IDQ_TRY(launch_axpbypcz(1.0, p, -1.0, y, 0.0, nullptr, gf, g.n * g.per, dtype, s));
+    return IDQ_OK;
+  }
+  void* tmp;
+  IDQ_TRY(ctx->ws.get(W_S, sbytes, &tmp));
+  StencilArgs a = stencil_base(ctx, g, gate);
+  a.in0 = p;
+  a.aux = y;
+  a.out = tmp;
+  a.mode = ctx->op_kind == IDQ_OP_BLUR_CIRC ? S_B_MINUS : S_TANH_WRES;
+  IDQ_TRY(launch_stencil(a, ctx->taps.data(), dtype, s));
+  StencilArgs b = stencil_base(ctx, g, gate);
+  b.in0 = tmp;
+  b.out = gf;
+  b.mode = S_BT;
+  return launch_stencil(b, ctx->taps.data(), dtype, s);
+}
+
+// Hessian of f at (x, y) along v into out.
+int data_hvp(idq_ctx* ctx, const Geometry& g, int dtype, const void* x, const void* y,
+             const void* v, void* out, hipStream_t s) {
+  const size_t sbytes = static_cast<size_t>(g.n) * g.per * elem_size(dtype);
+  if (ctx->op_kind == IDQ_OP_IDENTITY) return copy_state(v, out, sbytes, s);
+  void* tmp;
+  IDQ_TRY(ctx->ws.get(W_S, sbytes, &tmp));
+  StencilArgs a = stencil_base(ctx, g, nullptr);
+  if (ctx->op_kind == IDQ_OP_BLUR_CIRC) {
+    a.in0 = v;
+    a.mode = S_B;
+  } else {
+    a.in0 = x;
+    a.in1 = v;
+    a.aux = y;
+    a.mode = S_TANH_HESS;
+  }
+  a.out = tmp;
+  IDQ_TRY(launch_stencil(a, ctx->taps.data(), dtype, s));
+  StencilArgs b = stencil_base(ctx, g, nullptr);
+  b.in0 = tmp;
+  b.out = out;
+  b.mode = S_BT;
+  return launch_stencil(b, ctx->taps.data(), dtype, s);
+}
+
+// H_F(x) v = grad^2 f v + lambda H_g v into out.
+int obj_hvp(idq_ctx* ctx, const Geometry& g, int dtype, int prec, const void* x, const void* y,
+            const void* v, double lambda, void* out, hipStream_t s) {
+  const size_t sbytes = static_cast<size_t>(g.n) * g.per * elem_size(dtype);
+  void *hf, *hg;
+  IDQ_TRY(ctx->ws.get(W_HF, sbytes, &hf));
+  IDQ_TRY(data_hvp(ctx, g, dtype, x, y, v, hf, s));
+  if (ctx->L == 0 || lambda == 0.0) return copy_state(hf, out, sbytes, s);
+  IDQ_TRY(ctx->ws.get(W_HG, sbytes, &hg));
+  IDQ_TRY(net_hvp(ctx, g, prec, x, v, hg, s));
+  return launch_axpbypcz(1.0, hf, lambda, hg, 0.0, nullptr, out, g.n * g.per, dtype, s);
+}
+
+int dot(idq_ctx* ctx, const void* a, const void* b, long long count, int dtype, double* out,
+        hipStream_t s) {
+  void* part;
+  IDQ_TRY(ctx->ws.get(W_PART, 1024 * 8, &part));
+  return launch_dot(a, b, count, dtype, static_cast<double*>(part), 1024, out, s);
+}
+
+int power_iteration(idq_ctx* ctx, const Geometry& g, int dtype, int prec, const void* x,
+                    const void* y, const void* v0, double lambda, int iters, double* L,
+                    hipStream_t s) {
+  const size_t sbytes = static_cast<size_t>(g.n) * g.per * elem_size(dtype);
+  const long long cnt = g.n * g.per;
+  void *v, *w, *scal;
+  IDQ_TRY(ctx->ws.get(W_V, sbytes, &v));
+  IDQ_TRY(ctx->ws.get(W_W, sbytes, &w));
+  IDQ_TRY(ctx->ws.get(W_SCAL, 64, &scal));
+  double* sc = static_cast<double*>(scal);
+  IDQ_TRY(dot(ctx, v0, v0, cnt, dtype, sc, s));
+  IDQ_TRY(launch_scale_by(v0, v, cnt, sc, 1, dtype, s));
+  for (int it = 0; it < iters; ++it) {
+    IDQ_TRY(obj_hvp(ctx, g, dtype, prec, x, y, v, lambda, w, s));
+    IDQ_TRY(dot(ctx, v, w, cnt, dtype, sc + 1, s));
+    IDQ_TRY(dot(ctx, w, w, cnt, dtype, sc, s));
+    IDQ_TRY(launch_scale_by(w, v, cnt, sc, 1, dtype, s));
+  }
+  double hL = 0.0;
+  IDQ_HIP(hipMemcpyAsync(&hL, sc + 1, 8, hipMemcpyDeviceToHost, s));
+  IDQ_HIP(hipStreamSynchronize(s));
+  *L = hL;
+  return IDQ_OK;
+}
+
+int ensure_host_gate(idq_ctx* ctx, int n) {
+  if (ctx->host_gate_cap < n) {
+    if (ctx->host_gate) hipHostFree(ctx->host_gate);
+    ctx->host_gate = nullptr;
+    IDQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->host_gate), sizeof(int) * n));
+    ctx->host_gate_cap = n;
+  }
+  return IDQ_OK;
+}
+
+}  // namespace
+
+int ws_forward_internal(idq_ws* ws, const void* y, void* x0, int n, int c, int h, int w, int prec,
+                        hipStream_t s);  // ws.hip
+
+namespace {
+
+int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, int c, int h,
+               int w, int dtype, const idq_solve_opts* o, idq_solve_info* info, hipStream_t s) {
+  if (!y || !x_out || !o || !info) return fail(IDQ_E_INVAL, "null argument");
+  Geometry g;
+  IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+  IDQ_TRY(check_prec(dtype, o->conv_prec));
+  if (o->max_iter <= 0 && o->fixed_iters <= 0) return fail(IDQ_E_INVAL, "max_iter must be positive");
+  const bool use_net = ctx->L > 0 && o->lambda != 0.0;
+  const size_t es = elem_size(dtype);
+  const size_t sbytes = static_cast<size_t>(n) * g.per * es;
+  const long long cnt = n * g.per;
+  void *xb[2], *z, *gf, *q, *part, *state, *gate, *beta;
+  IDQ_TRY(ctx->ws.get(W_X0, sbytes, &xb[0]));
+  IDQ_TRY(ctx->ws.get(W_X1, sbytes, &xb[1]));
+  IDQ_TRY(ctx->ws.get(W_Z, sbytes, &z));
+  IDQ_TRY(ctx->ws.get(W_GF, sbytes, &gf));
+  IDQ_TRY(ctx->ws.get(W_Q, sbytes, &q));
+  const int nblk = static_cast<int>(std::min<long long>(64, (g.per + 4095) / 4096));
+  IDQ_TRY(ctx->ws.get(W_PART, static_cast<size_t>(n) * nblk * 3 * 8 + 1024 * 8, &part));
+  IDQ_TRY(ctx->ws.get(W_STATE, sizeof(ImgState) * n, &state));
+  IDQ_TRY(ctx->ws.get(W_GATE, sizeof(int) * n, &gate));
+  IDQ_TRY(ctx->ws.get(W_BETA, sizeof(double) * n, &beta));
+  // x^0 and x^{-1} = x^0
+  if (x0) {
+    IDQ_TRY(copy_state(x0, xb[0], sbytes, s));
+  } else if (o->init == IDQ_INIT_Y) {
+    IDQ_TRY(copy_state(y, xb[0], sbytes, s));
+  } else if (o->init == IDQ_INIT_ZERO) {
+    IDQ_HIP(hipMemsetAsync(xb[0], 0, sbytes, s));
+  } else if (o->init == IDQ_INIT_WARMSTART) {
+    if (!o->ws || dtype != IDQ_F32) return fail(IDQ_E_INVAL, "warm start needs a network and float32");
+    IDQ_TRY(ws_forward_internal(o->ws, y, xb[0], n, c, h, w, o->ws_prec, s));
+  } else {
+    return fail(IDQ_E_INVAL, "bad init");
+  }
+  IDQ_TRY(copy_state(xb[0], xb[1], sbytes, s));
+  // step size
+  double tau = o->tau;
+  if (tau <= 0.0) {
+    if (!o->power_v0) return fail(IDQ_E_INVAL, "tau == 0 needs power_v0");
+    const int pprec = o->conv_prec == IDQ_BF16 ? IDQ_F32 : o->conv_prec;
+    double L = 0.0;
+    IDQ_TRY(power_iteration(ctx, g, dtype, pprec, xb[0], y, o->power_v0, o->lambda,
+                            o->power_iters > 0 ? o->power_iters : 30, &L, s));
+    if (!(L > 0.0)) return fail(IDQ_E_NONFINITE, "power iteration gave a non-positive L");
+    tau = 0.9 / L;
+  }
+  // per-image state
+  const int first_gate = o->conv_prec == IDQ_BF16 ? G_LOW : G_FINAL;
+  std::vector<ImgState> hs(n);
+  for (auto& st : hs) {
+    std::memset(&st, 0, sizeof(st));
+    st.status = IDQ_ST_MAXITER;
+    st.prec = first_gate;
+    st.rel = INFINITY;
+    st.best_rel = INFINITY;
+  }
+  std::vector<int> hg(n, first_gate);
+  std::vector<double> hb(n, 0.0);
+  IDQ_HIP(hipMemcpyAsync(state, hs.data(), sizeof(ImgState) * n, hipMemcpyHostToDevice, s));
+  IDQ_HIP(hipMemcpyAsync(gate, hg.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  IDQ_HIP(hipMemcpyAsync(beta, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  IDQ_TRY(ensure_host_gate(ctx, n));
+
+  const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
+  const int poll = o->poll_every > 0 ? o->poll_every : 8;
+  const int final_prec = o->conv_prec == IDQ_BF16 ? IDQ_F32 : o->conv_prec;
+  bool low_live = o->conv_prec == IDQ_BF16;
+  const int* gp = static_cast<const int*>(gate);
+  const bool identity = ctx->op_kind == IDQ_OP_IDENTITY;
+
+  FinalizeArgs fa{};
+  fa.n = n;
+  fa.nblk = nblk;
+  fa.partials = static_cast<double*>(part);
+  fa.st = static_cast<ImgState*>(state);
+  fa.gate = static_cast<int*>(gate);
+  fa.beta_eff = static_cast<double*>(beta);
+  fa.beta = o->beta;
+  fa.tol = o->tol;
+  fa.restart_B2 = o->restart_B > 0.0 ? o->restart_B * o->restart_B : 0.0;
+  fa.switch_tol = o->switch_tol;
+  fa.switch_patience = o->switch_patience > 0 ? o->switch_patience : 10;
+  fa.max_iter = o->max_iter;
+  fa.fixed_iters = o->fixed_iters;
+
+  int t = 0;
+  while (t < limit) {
+    const int t_end = std::min(limit, t + poll);
+    for (; t < t_end; ++t) {
+      void* xa = xb[t % 2];
+      void* xp = xb[(t + 1) % 2];
+      IDQ_TRY(launch_extrap(xa, xp, z, static_cast<const double*>(beta), gp, n, g.per, dtype, s));
+      const void* p = o->grad_at == IDQ_GRAD_AT_CURRENT ? xa : z;
+      if (!identity) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false));
+      if (use_net) {
+        if (low_live) IDQ_TRY(net_grad(ctx, g, IDQ_BF16, p, q, gp, 1 << G_LOW, s));
+        IDQ_TRY(net_grad(ctx, g, final_prec, p, q, gp, 1 << G_FINAL, s));
+      }
+      UpdateArgs ua{};
+      ua.n = n;
+      ua.per = g.per;
+      ua.x = xa;
+      ua.z = z;
+      ua.gf = identity ? nullptr : gf;
+      ua.p = p;
+      ua.y = y;
+      ua.q = use_net ? q : nullptr;
+      ua.xn = xp;
+      ua.tau = tau;
+      ua.lambda = o->lambda;
+      ua.gate = gp;
+      ua.partials = static_cast<double*>(part);
+      ua.nblk = nblk;
+      IDQ_TRY(launch_update(ua, dtype, s));
+      fa.buf_index = (t + 1) % 2;
+      IDQ_TRY(launch_finalize(fa, s));
+    }
+    IDQ_HIP(hipMemcpyAsync(ctx->host_gate, gate, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    IDQ_HIP(hipStreamSynchronize(s));
+    bool any = false, anylow = false;
+    for (int i = 0; i < n; ++i) {
+      any |= ctx->host_gate[i] != G_DONE;
+      anylow |= ctx->host_gate[i] == G_LOW;
+    }
+    low_live = anylow;
+    if (!any) break;
+  }
+  IDQ_TRY(launch_gather_result(xb[0], xb[1], x_out, static_cast<const ImgState*>(state), n, g.per,
+                               dtype, s));
+  IDQ_HIP(hipMemcpyAsync(hs.data(), state, sizeof(ImgState) * n, hipMemcpyDeviceToHost, s));
+  IDQ_HIP(hipStreamSynchronize(s));
+  int rc = IDQ_OK;
+  for (int i = 0; i < n; ++i) {
+    info[i].iters = hs[i].it;
+    info[i].iters_low = hs[i].it_low;
+    info[i].restarts = hs[i].restarts;
+    info[i].status = hs[i].status;
+    info[i].rel = hs[i].rel;
+    info[i].tau = tau;
+    if (hs[i].status == IDQ_ST_NONFINITE) rc = IDQ_E_NONFINITE;
+    else if (hs[i].status == IDQ_ST_MAXITER && rc == IDQ_OK) rc = IDQ_W_MAXITER;
+  }
+  (void)cnt;
+  return rc;
+}
+
+int backward_impl(idq_ctx* ctx, const void* xbar, const void* y, const void* v, void* dtheta,
+                  double* dlambda, int n, int c, int h, int w, int dtype, const idq_bwd_opts* o,
+                  idq_bwd_info* info, hipStream_t s) {
+  if (!xbar || !y || !v || !dtheta || !o) return fail(IDQ_E_INVAL, "null argument");
+  if (ctx->L == 0) return fail(IDQ_E_INVAL, "no network");
+  Geometry g;
+  IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+  const int prec = dtype;  // the backward runs in the tensors' own arithmetic
+  IDQ_TRY(check_prec(dtype, prec));
+  const size_t sbytes = static_cast<size_t>(n) * g.per * elem_size(dtype);
+  const long long cnt = n * g.per;
+  void *u, *up, *un, *hw, *scal;
+  IDQ_TRY(ctx->ws.get(W_U, sbytes, &u));
+  IDQ_TRY(ctx->ws.get(W_UP, sbytes, &up));
+  IDQ_TRY(ctx->ws.get(W_UN, sbytes, &un));
+  IDQ_TRY(ctx->ws.get(W_W, sbytes, &hw));
+  IDQ_TRY(ctx->ws.get(W_SCAL, 64, &scal));
+  double* sc = static_cast<double*>(scal);
+  IDQ_TRY(copy_state(v, u, sbytes, s));
+  int iters = 0;
+  double rel = 0.0;
+  if (o->mode == IDQ_BWD_IMPLICIT) {
+    IDQ_TRY(copy_state(v, up, sbytes, s));
+    void* wv;
+    IDQ_TRY(ctx->ws.get(W_V, sbytes, &wv));
+    for (int j = 1; j <= o->adjoint_max_iter; ++j) {
+      // w = u + beta (u - up); un = w - tau H w + v
+      IDQ_TRY(launch_axpbypcz(1.0 + o->adjoint_beta, u, -o->adjoint_beta, up, 0.0, nullptr, wv, cnt,
+                              dtype, s));
+      IDQ_TRY(obj_hvp(ctx, g, dtype, prec, xbar, y, wv, o->lambda, hw, s));
+      IDQ_TRY(launch_axpbypcz(1.0, wv, -o->tau, hw, 1.0, v, un, cnt, dtype, s));
+      // rel = ||un - u|| / ||u||
+      IDQ_TRY(launch_axpbypcz(1.0, un, -1.0, u, 0.0, nullptr, up, cnt, dtype, s));
+      IDQ_TRY(dot(ctx, up, up, cnt, dtype, sc, s));
+      IDQ_TRY(dot(ctx, u, u, cnt, dtype, sc + 1, s));
+      double hsc[2];
+      IDQ_HIP(hipMemcpyAsync(hsc, sc, 16, hipMemcpyDeviceToHost, s));
+      IDQ_HIP(hipStreamSynchronize(s));
+      rel = std::sqrt(hsc[0] / std::max(hsc[1], 1e-300));
+      // rotate: up <- u, u <- un
+      void* tmp = up;
+      up = u;
+      u = un;
+      un = tmp;
+      iters = j;
+      if (!(rel >= o->adjoint_tol)) break;
+    }
+  }
+  // theta gradient from the forward-over-reverse pass along u
+  void* hgout;
+  IDQ_TRY(ctx->ws.get(W_HG, sbytes, &hgout));
+  IDQ_TRY(net_hvp(ctx, g, prec, xbar, u, hgout, s));
+  const double scale = o->tau * o->lambda;
+  const size_t abytes = static_cast<size_t>(g.pix()) * max_ch(ctx) * act_size(prec);
+  const long long pix = g.pix();
+  const int nchunk = static_cast<int>(std::max<long long>(1, std::min<long long>(256, pix / 1024)));
+  size_t off = 0;
+  for (int l = 0; l < ctx->L; ++l) {
+    const int ci = ctx->ch[l], co = ctx->ch[l + 1];
+    const int nslots = co * ci * 9 + co;
+    void* wgp;
+    IDQ_TRY(ctx->ws.get(W_WGPART, static_cast<size_t>(nchunk) * nslots * 8, &wgp));
+    void *gdd, *gd, *a0, *a1, *hprev = nullptr, *hdprev = nullptr;
+    if (l == ctx->L - 1) {
+      IDQ_TRY(ctx->ws.get(W_RD, sbytes, &gdd));
+      IDQ_TRY(ctx->ws.get(W_R, sbytes, &gd));
+    } else {
+      IDQ_TRY(ctx->ws.get(W_DDL0 + l, abytes, &gdd));
+      IDQ_TRY(ctx->ws.get(W_DL0 + l, abytes, &gd));
+    }
+    if (l > 0) {
+      IDQ_TRY(ctx->ws.get(W_H0 + l - 1, abytes, &hprev));
+      IDQ_TRY(ctx->ws.get(W_HD0 + l - 1, abytes, &hdprev));
+    }
+    const int gfmt = l == ctx->L - 1 ? F_NCHW : F_NHWC;
+    WgradArgs wa{};
+    wa.NI = g.NI;
+    wa.H = g.h;
+    wa.W = g.w;
+    wa.CI = ci;
+    wa.CO = co;
+    wa.g_fmt = gfmt;
+    wa.act = ctx->act;
+    wa.partials = static_cast<double*>(wgp);
+    wa.nchunk = nchunk;
+    // delta'_l corr a_{l-1}  (+ bias: sum delta'_l)
+    wa.g = gdd;
+    if (l == 0) {
+      wa.a_fmt = F_NCHW;
+      wa.a_pro = P_NONE;
+      wa.a0 = xbar;
+    } else {
+      wa.a_fmt = F_NHWC;
+      wa.a_pro = P_ACT;
+      wa.a0 = hprev;
+    }
+    wa.with_bias = 1;
+    IDQ_TRY(launch_wgrad(wa, prec, s));
+    char* dst = static_cast<char*>(dtheta) + off * elem_size(dtype);
+    IDQ_TRY(launch_reduce_chunks(static_cast<double*>(wgp), nchunk, nslots, scale, dst, 0, dtype, s));
+    // delta_l corr a'_{l-1}
+    wa.g = gd;
+    if (l == 0) {
+      wa.a0 = u;
+      wa.a_pro = P_NONE;
+    } else {
+      wa.a0 = hprev;
+      wa.a1 = hdprev;
+      wa.a_pro = P_JVP;
+    }
+    wa.with_bias = 0;
+    IDQ_TRY(launch_wgrad(wa, prec, s));
+    IDQ_TRY(launch_reduce_chunks(static_cast<double*>(wgp), nchunk, co * ci * 9, scale, dst, 1,
+                                 dtype, s));
+    off += static_cast<size_t>(nslots);
+  }
+  // dlambda = -tau <grad g(xbar), u>
+  if (dlambda) {
+    void* q;
+    IDQ_TRY(ctx->ws.get(W_Q, sbytes, &q));
+    IDQ_TRY(net_grad(ctx, g, prec, xbar, q, nullptr, 0, s));
+    IDQ_TRY(dot(ctx, q, u, cnt, dtype, sc + 2, s));
+    double d = 0.0;
+    IDQ_HIP(hipMemcpyAsync(&d, sc + 2, 8, hipMemcpyDeviceToHost, s));
+    IDQ_HIP(hipStreamSynchronize(s));
+    *dlambda = -o->tau * d;
+  }
+  IDQ_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->adjoint_iters = iters;
+    info->adjoint_rel = rel;
+  }
+  return IDQ_OK;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(IDQ_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(IDQ_E_INVAL, e.what());
+  } catch (...) {
+    return fail(IDQ_E_INVAL, "unknown exception");
+  }
+}
+
+int set_device(const idq_ctx* ctx) {
+  IDQ_HIP(hipSetDevice(ctx->device));
+  return IDQ_OK;
+}
+
+}  // namespace
+}  // namespace idq
+
+using namespace idq;
+
+extern "C" {
+
+const char* idq_last_error(void) { return g_err.c_str(); }
+int idq_version(void) { return 10000; }
+
+void idq_solve_opts_default(idq_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->beta = 0.5;
+  o->tau = 0.0;
+  o->lambda = 1.0;
+  o->tol = 1e-4;
+  o->max_iter = 1000;
+  o->fixed_iters = 0;
+  o->restart_B = 0.0;
+  o->grad_at = IDQ_GRAD_AT_EXTRAPOLATED;
+  o->conv_prec = IDQ_F32;
+  o->switch_tol = 1e-3;
+  o->switch_patience = 10;
+  o->power_iters = 30;
+  o->poll_every = 8;
+  o->init = IDQ_INIT_Y;
+  o->ws_prec = IDQ_BF16;
+  o->use_graph = 0;
+}
+
+int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, int device) {
+  return guarded([&]() -> int {
+    if (!out || !op) return fail(IDQ_E_INVAL, "null argument");
+    *out = nullptr;
+    int ndev = 0;
+    IDQ_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(IDQ_E_INVAL, "bad device index");
+    IDQ_HIP(hipSetDevice(device));
+    auto* ctx = new idq_ctx();
+    ctx->device = device;
+    if (net && net->n_layers > 0) {
+      if (net->n_layers > IDQ_MAX_LAYERS || !net->params) {
+        delete ctx;
+        return fail(IDQ_E_INVAL, "bad network description");
+      }
+      ctx->L = net->n_layers;
+      ctx->act = net->act;
+      if (net->act != IDQ_ACT_SOFTPLUS && net->act != IDQ_ACT_IDENTITY) {
+        delete ctx;
+        return fail(IDQ_E_INVAL, "bad activation");
+      }
+      size_t total = 0;
+      for (int l = 0; l <= ctx->L; ++l) {
+        ctx->ch[l] = net->channels[l];
+        if (ctx->ch[l] <= 0 || ctx->ch[l] > 1024) {
+          delete ctx;
+          return fail(IDQ_E_INVAL, "bad channel count");
+        }
+      }
+      if (ctx->ch[0] != ctx->ch[ctx->L]) {
+        delete ctx;
+        return fail(IDQ_E_INVAL, "network must map c channels to c channels");
+      }
+      for (int l = 0; l < ctx->L; ++l)
+        total += static_cast<size_t>(ctx->ch[l + 1]) * ctx->ch[l] * 9 + ctx->ch[l + 1];
+      ctx->params.assign(net->params, net->params + total);
+    }
+    ctx->op_kind = op->kind;
+    if (op->kind != IDQ_OP_IDENTITY) {
+      if (op->kind != IDQ_OP_BLUR_CIRC && op->kind != IDQ_OP_TANH_BLUR) {
+        delete ctx;
+        return fail(IDQ_E_INVAL, "bad operator kind");
+      }
+      if (!op->taps || op->kh <= 0 || op->kw <= 0 || op->kh % 2 == 0 || op->kw % 2 == 0 ||
+          op->kh > 9 || op->kw > 9) {
+        delete ctx;
+        return fail(IDQ_E_INVAL, "blur taps must be odd-sized, at most 9x9");
+      }
+      ctx->kh = op->kh;
+      ctx->kw = op->kw;
+      ctx->taps.assign(op->taps, op->taps + op->kh * op->kw);
+      ctx->gain = op->gain;
+      if (op->kind == IDQ_OP_TANH_BLUR && !(op->gain > 0.0)) {
+        delete ctx;
+        return fail(IDQ_E_INVAL, "tanh-blur gain must be positive");
+      }
+    }
+    if (ctx->L > 0) {
+      int rc = pack_weights(ctx);
+      if (rc < 0) {
+        free_layers(ctx);
+        delete ctx;
+        return rc;
+      }
+    }
+    *out = ctx;
+    return IDQ_OK;
+  });
+}
+
+int idq_destroy(idq_ctx* ctx) {
+  if (!ctx) return IDQ_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  free_layers(ctx);
+  ctx->ws.release();
+  if (ctx->host_gate) hipHostFree(ctx->host_gate);
+  delete ctx;
+  return IDQ_OK;
+}
+
+long long idq_num_params(const idq_ctx* ctx) {
+  return ctx ? static_cast<long long>(ctx->params.size()) : 0;
+}
+
+int idq_set_params(idq_ctx* ctx, const double* params, long long count) {
+  return guarded([&]() -> int {
+    if (!ctx || !params) return fail(IDQ_E_INVAL, "null argument");
+    if (count != static_cast<long long>(ctx->params.size()))
+      return fail(IDQ_E_INVAL, "parameter count mismatch");
+    IDQ_TRY(set_device(ctx));
+    IDQ_HIP(hipDeviceSynchronize());
+    ctx->params.assign(params, params + count);
+    return pack_weights(ctx);
+  });
+}
+
+int idq_apply_A(idq_ctx* ctx, const void* x, void* Ax, int n, int c, int h, int w, int dtype,
+                void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !x || !Ax) return fail(IDQ_E_INVAL, "null argument");
+    if (dtype != IDQ_F64 && dtype != IDQ_F32) return fail(IDQ_E_INVAL, "bad dtype");
+    Geometry g;
+    IDQ_TRY(set_device(ctx));
+    IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->op_kind == IDQ_OP_IDENTITY)
+      return copy_state(x, Ax, static_cast<size_t>(n) * g.per * elem_size(dtype), s);
+    StencilArgs a = stencil_base(ctx, g, nullptr);
+    a.in0 = x;
+    a.out = Ax;
+    a.mode = ctx->op_kind == IDQ_OP_BLUR_CIRC ? S_B : S_TANH_A;
+    return launch_stencil(a, ctx->taps.data(), dtype, s);
+  });
+}
+
+int idq_apply_AT(idq_ctx* ctx, const void* x, const void* v, void* out, int n, int c, int h,
+                 int w, int dtype, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !v || !out) return fail(IDQ_E_INVAL, "null argument");
+    if (dtype != IDQ_F64 && dtype != IDQ_F32) return fail(IDQ_E_INVAL, "bad dtype");
+    Geometry g;
+    IDQ_TRY(set_device(ctx));
+    IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t sbytes = static_cast<size_t>(n) * g.per * elem_size(dtype);
+    if (ctx->op_kind == IDQ_OP_IDENTITY) return copy_state(v, out, sbytes, s);
+    const void* src = v;
+    if (ctx->op_kind == IDQ_OP_TANH_BLUR) {
+      if (!x) return fail(IDQ_E_INVAL, "the tanh-blur adjoint needs the linearisation point x");
+      void* tmp;
+      IDQ_TRY(ctx->ws.get(W_S, sbytes, &tmp));
+      StencilArgs a = stencil_base(ctx, g, nullptr);
+      a.in0 = x;
+      a.aux = v;
+      a.out = tmp;
+      a.mode = S_TANH_JTW;
+      IDQ_TRY(launch_stencil(a, ctx->taps.data(), dtype, s));
+      src = tmp;
+    }
+    StencilArgs b = stencil_base(ctx, g, nullptr);
+    b.in0 = src;
+    b.out = out;
+    b.mode = S_BT;
+    return launch_stencil(b, ctx->taps.data(), dtype, s);
+  });
+}
+
+int idq_grad_data(idq_ctx* ctx, const void* x, const void* y, void* grad, int n, int c, int h,
+                  int w, int dtype, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !x || !y || !grad) return fail(IDQ_E_INVAL, "null argument");
+    if (dtype != IDQ_F64 && dtype != IDQ_F32) return fail(IDQ_E_INVAL, "bad dtype");
+    Geometry g;
+    IDQ_TRY(set_device(ctx));
+    IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+    return data_grad(ctx, g, dtype, x, y, grad, nullptr, static_cast<hipStream_t>(stream), true);
+  });
+}
+
+int idq_grad_reg(idq_ctx* ctx, const void* x, void* grad, double* g_val, int n, int c, int h,
+                 int w, int dtype, int conv_prec, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !x || !grad) return fail(IDQ_E_INVAL, "null argument");
+    if (ctx->L == 0) return fail(IDQ_E_INVAL, "context has no network");
+    IDQ_TRY(check_prec(dtype, conv_prec));
+    Geometry g;
+    IDQ_TRY(set_device(ctx));
+    IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    IDQ_TRY(net_grad(ctx, g, conv_prec, x, grad, nullptr, 0, s));
+    if (g_val) {
+      void *r, *part, *scal;
+      IDQ_TRY(ctx->ws.get(W_R, static_cast<size_t>(n) * g.per * elem_size(dtype), &r));
+      IDQ_TRY(ctx->ws.get(W_PART, static_cast<size_t>(n) * 64 * 8 + 1024 * 8, &part));
+      IDQ_TRY(ctx->ws.get(W_SCAL, std::max<size_t>(64, sizeof(double) * n), &scal));
+      IDQ_TRY(launch_half_sqnorm_per_image(r, n, g.per, dtype, static_cast<double*>(part), 64,
+                                           static_cast<double*>(scal), s));
+      IDQ_HIP(hipMemcpyAsync(g_val, scal, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+      IDQ_HIP(hipStreamSynchronize(s));
+    }
+    return IDQ_OK;
+  });
+}
+
+int idq_hvp(idq_ctx* ctx, const void* x, const void* y, const void* v, void* out, double lambda,
+            int which, int n, int c, int h, int w, int dtype, int conv_prec, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !x || !v || !out) return fail(IDQ_E_INVAL, "null argument");
+    IDQ_TRY(check_prec(dtype, conv_prec));
+    if (conv_prec == IDQ_BF16) return fail(IDQ_E_UNSUPPORTED, "HVP is float32/float64 only");
+    Geometry g;
+    IDQ_TRY(set_device(ctx));
+    IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (which == 0) {
+      if (ctx->L == 0) return fail(IDQ_E_INVAL, "context has no network");
+      return net_hvp(ctx, g, conv_prec, x, v, out, s);
+    }
+    if (!y) return fail(IDQ_E_INVAL, "objective HVP needs y");
+    return obj_hvp(ctx, g, dtype, conv_prec, x, y, v, lambda, out, s);
+  });
+}
+
+int idq_lipschitz(idq_ctx* ctx, const void* x, const void* y, const void* v0, double lambda,
+                  int iters, int n, int c, int h, int w, int dtype, int conv_prec, double* L) {
+  return guarded([&]() -> int {
+    if (!ctx || !x || !y || !v0 || !L) return fail(IDQ_E_INVAL, "null argument");
+    IDQ_TRY(check_prec(dtype, conv_prec));
+    if (conv_prec == IDQ_BF16) return fail(IDQ_E_UNSUPPORTED, "HVP is float32/float64 only");
+    if (iters <= 0) return fail(IDQ_E_INVAL, "iters must be positive");
+    Geometry g;
+    IDQ_TRY(set_device(ctx));
+    IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+    return power_iteration(ctx, g, dtype, conv_prec, x, y, v0, lambda, iters, L, nullptr);
+  });
+}
+
+int idq_solve(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, int c, int h,
+              int w, int dtype, const idq_solve_opts* opts, idq_solve_info* info, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(IDQ_E_INVAL, "null context");
+    IDQ_TRY(set_device(ctx));
+    return solve_impl(ctx, y, x0, x_out, n, c, h, w, dtype, opts, info,
+                      static_cast<hipStream_t>(stream));
+  });
+}
+
+int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_dx, void* dtheta,
+                 double* dlambda, int n, int c, int h, int w, int dtype, const idq_bwd_opts* opts,
+                 idq_bwd_info* info, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(IDQ_E_INVAL, "null context");
+    IDQ_TRY(set_device(ctx));
+    return backward_impl(ctx, xbar, y, dl_dx, dtheta, dlambda, n, c, h, w, dtype, opts, info,
+                         static_cast<hipStream_t>(stream));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Shared definitions of the i-DEQ HIP library (device helpers, error plumbing).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "../../include/idq.h"
+
+namespace idq {
+
+// ---------------------------------------------------------------------------
+// bfloat16 storage: 16-bit payload, converted by round-to-nearest-even.
+// ---------------------------------------------------------------------------
+struct bf16 {
+  uint16_t u;
+};
+
+__host__ __device__ inline float bf2f(bf16 v) {
+  union { uint32_t i; float f; } c;
+  c.i = static_cast<uint32_t>(v.u) << 16;
+  return c.f;
+}
+
+__host__ __device__ inline bf16 f2bf(float f) {
+  union { uint32_t i; float f; } c;
+  c.f = f;
+  uint32_t x = c.i;
+  bf16 r;
+  if ((x & 0x7f800000u) == 0x7f800000u && (x & 0x007fffffu)) {  // NaN stays NaN
+    r.u = static_cast<uint16_t>((x >> 16) | 0x0040u);
+    return r;
+  }
+  x += 0x7fffu + ((x >> 16) & 1u);
+  r.u = static_cast<uint16_t>(x >> 16);
+  return r;
+}
+
+__host__ __device__ inline float round_bf(float f) { return bf2f(f2bf(f)); }
+
+// Load/store of an activation element of any storage type as math type TM.
+template <typename TM, typename TS>
+__device__ inline TM ld(const TS* p, size_t i) { return static_cast<TM>(p[i]); }
+template <>
+__device__ inline float ld<float, bf16>(const bf16* p, size_t i) { return bf2f(p[i]); }
+template <typename TS, typename TM>
+__device__ inline void st(TS* p, size_t i, TM v) { p[i] = static_cast<TS>(v); }
+template <>
+__device__ inline void st<bf16, float>(bf16* p, size_t i, float v) { p[i] = f2bf(v); }
+
+// ---------------------------------------------------------------------------
+// Activation (SoftPlus with beta = 1, no threshold) and its derivatives.
+// ---------------------------------------------------------------------------
+__device__ inline float softplus_f(float t) { return fmaxf(t, 0.f) + log1pf(expf(-fabsf(t))); }
+__device__ inline double softplus_f(double t) { return fmax(t, 0.0) + log1p(exp(-fabs(t))); }
+__device__ inline float sigmoid_f(float t) {
+  float e = expf(-fabsf(t));
+  return t >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+}
+__device__ inline double sigmoid_f(double t) {
+  double e = exp(-fabs(t));
+  return t >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+}
+
+template <int ACT, typename T>
+__device__ inline T act_fn(T t) { return ACT == IDQ_ACT_SOFTPLUS ? softplus_f(t) : t; }
+template <int ACT, typename T>
+__device__ inline T dact_fn(T t) { return ACT == IDQ_ACT_SOFTPLUS ? sigmoid_f(t) : T(1); }
+template <int ACT, typename T>
+__device__ inline T d2act_fn(T t) {
+  if (ACT == IDQ_ACT_SOFTPLUS) {
+    T s = sigmoid_f(t);
+    return s * (T(1) - s);
+  }
+  return T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Errors: thread-local message, status codes of idq.h.
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define IDQ_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::idq::fail(IDQ_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define IDQ_TRY(expr)            \
+  do {                           \
+    int s_ = (expr);             \
+    if (s_ < 0) return s_;       \
+  } while (0)
+
+inline size_t elem_size(int dtype) { return dtype == IDQ_F64 ? 8 : (dtype == IDQ_F32 ? 4 : 2); }
+
+}  // namespace idq

@@ -1,0 +1,61 @@
+// Internal context of the i-DEQ library: network, operator, packed weights and
+// a grow-only device workspace.
+#pragma once
+
+#include <vector>
+
+#include "kernels.h"
+
+namespace idq {
+
+// Workspace slots.  Each slot is one device allocation that only grows.
+enum Slot {
+  W_X0, W_X1, W_Z, W_GF, W_S, W_Q, W_R, W_RD, W_T, W_HG, W_HF, W_V, W_W, W_U, W_UP, W_UN,
+  W_PART, W_STATE, W_GATE, W_BETA, W_SCAL, W_WGPART, W_TMP0, W_TMP1,
+  W_H0,                              // W_H0 + l     : h_{l+1}         (l < L-1)
+  W_HD0 = W_H0 + IDQ_MAX_LAYERS,     // W_HD0 + l    : h'_{l+1}
+  W_DL0 = W_HD0 + IDQ_MAX_LAYERS,    // W_DL0 + l    : delta_{l+1}
+  W_DDL0 = W_DL0 + IDQ_MAX_LAYERS,   // W_DDL0 + l   : delta'_{l+1}
+  W_NSLOTS = W_DDL0 + IDQ_MAX_LAYERS
+};
+
+struct Workspace {
+  void* ptr[W_NSLOTS] = {};
+  size_t cap[W_NSLOTS] = {};
+  int get(int slot, size_t bytes, void** out);
+  void release();
+};
+
+struct LayerW {
+  int ci = 0, co = 0;
+  // per precision (IDQ_F64/F32/BF16): direct forward and transposed weights
+  // [co][ci][9] / [ci][co][9] in the math type, bias [co], MFMA-packed copies.
+  void* fwd[3] = {};
+  void* tr[3] = {};
+  void* bias[3] = {};
+  void* fwd_mfma[3] = {};
+  void* tr_mfma[3] = {};
+};
+
+struct Geometry {
+  int n, c, h, w;      // solver images
+  int NI, img_div;     // net images and the net-image -> image divisor
+  long long per;       // c * h * w
+  long long pix() const { return static_cast<long long>(NI) * h * w; }
+};
+
+}  // namespace idq
+
+struct idq_ctx {
+  int device = 0;
+  int L = 0, act = IDQ_ACT_SOFTPLUS;
+  int ch[IDQ_MAX_LAYERS + 1] = {};
+  std::vector<double> params;
+  std::vector<idq::LayerW> layers;
+  int op_kind = IDQ_OP_IDENTITY, kh = 0, kw = 0;
+  double gain = 2.0;
+  std::vector<double> taps;
+  idq::Workspace ws;
+  int* host_gate = nullptr;  // pinned, for polling
+  int host_gate_cap = 0;
+};

@@ -1,0 +1,137 @@
+// Zero-padded 3x3 conv passes of the regularizer network N_theta
+// (the conv layers inside g(x) = 1/2 ||x - N(x)||^2, eq. GS).
+//
+// Two kernel families share one argument block (ConvArgs):
+//   * conv_direct: one thread per (pixel, 16 output channels), scalar FMA in the
+//     math type.  Used for float64 and for shapes the MFMA kernels do not cover.
+//   * conv_mfma (k_conv_mfma.hip): implicit GEMM on the gfx950 matrix cores.
+// Every pass is   acc[co](p) = sum_{ci, tap} W[co][ci][tap] * a[ci](p + off(tap))
+// with the operand a produced by the prologue (Pro) and the result consumed by
+// the epilogue (Epi); see kernels.h.
+#include "kernels.h"
+
+namespace idq {
+
+namespace {
+
+template <typename TM, typename TS, typename TA>
+__device__ inline TM load_operand(const ConvArgs& a, int ni, int ci, int yy, int xx) {
+  if (a.in_fmt == F_NCHW) {
+    size_t idx = ((static_cast<size_t>(ni) * a.CI + ci) * a.H + yy) * a.W + xx;
+    return ld<TM>(static_cast<const TS*>(a.in0), idx);
+  }
+  size_t idx = ((static_cast<size_t>(ni) * a.H + yy) * a.W + xx) * a.CI + ci;
+  TM v = ld<TM>(static_cast<const TA*>(a.in0), idx);
+  if (a.pro == P_ACT) {
+    return a.act == IDQ_ACT_SOFTPLUS ? softplus_f(v) : v;
+  }
+  if (a.pro == P_JVP) {
+    TM hd = ld<TM>(static_cast<const TA*>(a.in1), idx);
+    return (a.act == IDQ_ACT_SOFTPLUS ? sigmoid_f(v) : TM(1)) * hd;
+  }
+  return v;
+}
+
+template <typename TM, typename TS, typename TA, bool RBF>
+__global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
+  const int HW = a.H * a.W;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int ni = blockIdx.y;
+  const int co0 = blockIdx.z * 16;
+  if (p >= HW) return;
+  if (!gate_open(a.gate, a.gate_mask, ni / a.img_div)) return;
+  const int y = p / a.W, x = p - (p / a.W) * a.W;
+  const int nco = min(16, a.CO - co0);
+  const TM* w = static_cast<const TM*>(a.wgt);
+  TM acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = TM(0);
+  for (int ci = 0; ci < a.CI; ++ci) {
+    for (int t = 0; t < 9; ++t) {
+      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+      if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) continue;
+      TM v = load_operand<TM, TS, TA>(a, ni, ci, yy, xx);
+      if (RBF) v = static_cast<TM>(round_bf(static_cast<float>(v)));
+      const TM* wp = w + (static_cast<size_t>(co0) * a.CI + ci) * 9 + t;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j < nco) acc[j] += wp[static_cast<size_t>(j) * a.CI * 9] * v;
+    }
+  }
+  const TM* bias = static_cast<const TM*>(a.bias);
+  const bool sp = a.act == IDQ_ACT_SOFTPLUS;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (j >= nco) break;
+    const int co = co0 + j;
+    const TM b = bias ? bias[co] : TM(0);
+    if (a.out_fmt == F_NCHW) {
+      size_t o = ((static_cast<size_t>(ni) * a.CO + co) * a.H + y) * a.W + x;
+      TS* out = static_cast<TS*>(a.out0);
+      const TS* e0 = static_cast<const TS*>(a.e0);
+      TM r;
+      switch (a.epi) {
+        case E_STORE: r = acc[j] + b; break;
+        case E_RES: r = ld<TM>(e0, o) - (acc[j] + b); break;
+        case E_SUB: r = ld<TM>(e0, o) - acc[j]; break;
+        default: r = acc[j]; break;
+      }
+      st(out, o, r);
+    } else {
+      size_t o = ((static_cast<size_t>(ni) * a.H + y) * a.W + x) * a.CO + co;
+      TA* out = static_cast<TA*>(a.out0);
+      const TA* e0 = static_cast<const TA*>(a.e0);
+      switch (a.epi) {
+        case E_STORE: st(out, o, acc[j] + b); break;
+        case E_RAW: st(out, o, acc[j]); break;
+        case E_DELTA: {
+          TM h = ld<TM>(e0, o);
+          st(out, o, (sp ? sigmoid_f(h) : TM(1)) * acc[j]);
+          break;
+        }
+        case E_DDOT: {
+          TM h = ld<TM>(e0, o);
+          TM hd = ld<TM>(static_cast<const TA*>(a.e1), o);
+          TM t = ld<TM>(static_cast<const TA*>(a.e2), o);
+          TM s1 = sp ? sigmoid_f(h) : TM(1);
+          TM s2 = sp ? s1 * (TM(1) - s1) : TM(0);
+          st(out, o, s2 * hd * t + s1 * acc[j]);
+          st(static_cast<TA*>(a.out1), o, s1 * t);
+          break;
+        }
+        case E_RES: st(out, o, ld<TM>(e0, o) - (acc[j] + b)); break;
+        case E_SUB: st(out, o, ld<TM>(e0, o) - acc[j]); break;
+        default: break;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int launch_conv_mfma(const ConvArgs& a, int prec, hipStream_t s);  // k_conv_mfma.hip
+
+int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
+  if (a.NI <= 0 || a.H <= 0 || a.W <= 0) return IDQ_OK;
+  if (prec != PREC_F64 && a.wmfma && mfma_supported(prec, a.CI, a.CO))
+    return launch_conv_mfma(a, prec, s);
+  dim3 grid((a.H * a.W + 255) / 256, a.NI, (a.CO + 15) / 16);
+  if (grid.y > 65535) return fail(IDQ_E_INVAL, "too many images in one conv pass");
+  switch (prec) {
+    case PREC_F64:
+      conv_direct_kernel<double, double, double, false><<<grid, 256, 0, s>>>(a);
+      break;
+    case PREC_F32:
+      conv_direct_kernel<float, float, float, false><<<grid, 256, 0, s>>>(a);
+      break;
+    case PREC_BF16:
+      conv_direct_kernel<float, float, bf16, true><<<grid, 256, 0, s>>>(a);
+      break;
+    default:
+      return fail(IDQ_E_INVAL, "bad conv precision");
+  }
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+}  // namespace idq

@@ -1,0 +1,536 @@
+// Bandwidth-bound kernels of the i-DEQ iteration: circular blur stencils of the
+// forward operator, the inertial extrapolation, the fused update with its
+// float64 residual partial sums, the per-image finalize step (stopping rule,
+// restart, precision phase) and deterministic float64 reductions.
+#include "kernels.h"
+
+namespace idq {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T>
+__device__ inline bool finite_v(T v) { return isfinite(v); }
+
+// Fixed-order block reduction of up to three float64 sums (deterministic).
+__device__ inline void block_sum3(double& a, double& b, double& c) {
+  __shared__ double red[3][kBlock];
+  const int t = threadIdx.x;
+  red[0][t] = a;
+  red[1][t] = b;
+  red[2][t] = c;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      red[0][t] += red[0][t + o];
+      red[1][t] += red[1][t + o];
+      red[2][t] += red[2][t + o];
+    }
+    __syncthreads();
+  }
+  a = red[0][0];
+  b = red[1][0];
+  c = red[2][0];
+}
+
+// ---------------------------------------------------------------------------
+// Circular stencil (correlation with up to 9x9 taps) on 16x16 output tiles.
+// The (16+kh-1) x (16+kw-1) input tile is staged in LDS with modular wrap.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 16;
+constexpr int kMaxTap = 9;
+constexpr int kLds = (kTile + kMaxTap - 1) * (kTile + kMaxTap - 1);
+
+template <typename T>
+struct Taps {
+  T k[kMaxTap * kMaxTap];
+};
+
+__device__ inline int wrap(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, Taps<T> taps) {
+  __shared__ T tile0[kLds];
+  __shared__ T tile1[MODE == S_TANH_HESS ? kLds : 1];
+  const int plane = blockIdx.z;
+  if (a.gate && a.gate[plane / a.plane_div] == G_DONE) return;
+  const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
+  const int ry = (a.kh - 1) / 2, rx = (a.kw - 1) / 2;
+  const int LH = kTile + a.kh - 1, LW = kTile + a.kw - 1;
+  const size_t pbase = static_cast<size_t>(plane) * a.H * a.W;
+  const T* in0 = static_cast<const T*>(a.in0) + pbase;
+  const T* in1 = static_cast<const T*>(a.in1) + (MODE == S_TANH_HESS ? pbase : 0);
+  for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+    const int ly = i / LW, lx = i - (i / LW) * LW;
+    const int gy = wrap(ty0 - ry + ly, a.H), gx = wrap(tx0 - rx + lx, a.W);
+    tile0[i] = in0[static_cast<size_t>(gy) * a.W + gx];
+    if (MODE == S_TANH_HESS) tile1[i] = in1[static_cast<size_t>(gy) * a.W + gx];
+  }
+  __syncthreads();
+  const int ly = threadIdx.x / kTile, lx = threadIdx.x % kTile;
+  const int oy = ty0 + ly, ox = tx0 + lx;
+  if (oy >= a.H || ox >= a.W) return;
+  T s0 = T(0), s1 = T(0);
+  for (int p = 0; p < a.kh; ++p)
+    for (int q = 0; q < a.kw; ++q) {
+      const T kv = taps.k[p * a.kw + q];
+      s0 += kv * tile0[(ly + p) * LW + lx + q];
+      if (MODE == S_TANH_HESS) s1 += kv * tile1[(ly + p) * LW + lx + q];
+    }
+  const size_t o = pbase + static_cast<size_t>(oy) * a.W + ox;
+  T* out = static_cast<T*>(a.out);
+  const T* aux = static_cast<const T*>(a.aux);
+  const T g = static_cast<T>(a.gain);
+  const T tg = tanh(g);
+  const T c1 = g / tg;
+  switch (MODE) {
+    case S_B:
+    case S_BT: out[o] = s0; break;
+    case S_B_MINUS: out[o] = s0 - aux[o]; break;
+    case S_TANH_A: out[o] = tanh(g * s0) / tg; break;
+    case S_TANH_WRES: {
+      const T t = tanh(g * s0);
+      out[o] = c1 * (T(1) - t * t) * (t / tg - aux[o]);
+      break;
+    }
+    case S_TANH_JTW: {
+      const T t = tanh(g * s0);
+      out[o] = c1 * (T(1) - t * t) * aux[o];
+      break;
+    }
+    case S_TANH_HESS: {
+      const T t = tanh(g * s0);
+      const T sech2 = T(1) - t * t;
+      const T curv = T(-2) * g * g / tg * t * sech2;
+      out[o] = s1 * (c1 * c1 * sech2 * sech2 + (t / tg - aux[o]) * curv);
+      break;
+    }
+  }
+}
+
+template <typename T>
+int stencil_dispatch(const StencilArgs& a, const double* taps_host, hipStream_t s) {
+  Taps<T> tp;
+  const bool flip = a.mode == S_BT;
+  for (int p = 0; p < a.kh; ++p)
+    for (int q = 0; q < a.kw; ++q) {
+      const int sp = flip ? a.kh - 1 - p : p, sq = flip ? a.kw - 1 - q : q;
+      tp.k[p * a.kw + q] = static_cast<T>(taps_host[sp * a.kw + sq]);
+    }
+  dim3 grid((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile, a.NP);
+  switch (a.mode) {
+    case S_B: stencil_kernel<T, S_B><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_BT: stencil_kernel<T, S_BT><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_B_MINUS: stencil_kernel<T, S_B_MINUS><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_A: stencil_kernel<T, S_TANH_A><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_WRES: stencil_kernel<T, S_TANH_WRES><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_JTW: stencil_kernel<T, S_TANH_JTW><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_HESS: stencil_kernel<T, S_TANH_HESS><<<grid, kBlock, 0, s>>>(a, tp); break;
+    default: return fail(IDQ_E_INVAL, "bad stencil mode");
+  }
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels over n images of `per` elements (grid: blocks x images).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void extrap_kernel(const T* x, const T* xp, T* z,
+                                                      const double* beta_eff, const int* gate,
+                                                      long long per) {
+  const int img = blockIdx.y;
+  if (gate && gate[img] == G_DONE) return;
+  const T b = static_cast<T>(beta_eff[img]);
+  const size_t base = static_cast<size_t>(img) * per;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < per;
+       i += (long long)gridDim.x * kBlock) {
+    const T xv = x[base + i];
+    z[base + i] = xv + b * (xv - xp[base + i]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a) {
+  const int img = blockIdx.y;
+  const int blk = blockIdx.x;
+  if (a.gate && a.gate[img] == G_DONE) return;
+  const size_t base = static_cast<size_t>(img) * a.per;
+  const long long chunk = (a.per + a.nblk - 1) / a.nblk;
+  const long long lo = blk * chunk;
+  const long long hi = lo + chunk < a.per ? lo + chunk : a.per;
+  const T* x = static_cast<const T*>(a.x) + base;
+  const T* z = static_cast<const T*>(a.z) + base;
+  const T* gf = a.gf ? static_cast<const T*>(a.gf) + base : nullptr;
+  const T* p = a.p ? static_cast<const T*>(a.p) + base : nullptr;
+  const T* y = a.y ? static_cast<const T*>(a.y) + base : nullptr;
+  const T* q = a.q ? static_cast<const T*>(a.q) + base : nullptr;
+  T* xn = static_cast<T*>(a.xn) + base;
+  const T tau = static_cast<T>(a.tau), lam = static_cast<T>(a.lambda);
+  double s1 = 0.0, s0 = 0.0, nf = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const T xv = x[i];
+    const T g = gf ? gf[i] : p[i] - y[i];
+    const T qv = q ? q[i] : T(0);
+    const T v = z[i] - tau * (g + lam * qv);
+    xn[i] = v;
+    const double d = static_cast<double>(v) - static_cast<double>(xv);
+    s1 += d * d;
+    s0 += static_cast<double>(xv) * static_cast<double>(xv);
+    if (!finite_v(v)) nf += 1.0;
+  }
+  block_sum3(s1, s0, nf);
+  if (threadIdx.x == 0) {
+    double* o = a.partials + (static_cast<size_t>(img) * a.nblk + blk) * 3;
+    o[0] = s1;
+    o[1] = s0;
+    o[2] = nf;
+  }
+}
+
+__global__ void finalize_kernel(FinalizeArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  ImgState s = a.st[i];
+  if (s.done) return;
+  double s1 = 0.0, s0 = 0.0, nf = 0.0;
+  const double* p = a.partials + static_cast<size_t>(i) * a.nblk * 3;
+  for (int b = 0; b < a.nblk; ++b) {
+    s1 += p[3 * b];
+    s0 += p[3 * b + 1];
+    nf += p[3 * b + 2];
+  }
+  s.it += 1;
+  s.kr += 1;
+  s.S += s1;
+  const double rel = s0 > 0.0 ? sqrt(s1 / s0) : (s1 > 0.0 ? INFINITY : 0.0);
+  s.rel = rel;
+  s.last_buf = a.buf_index;
+  int gate = s.prec;
+  if (nf > 0.0 || !isfinite(s1)) {
+    s.status = IDQ_ST_NONFINITE;
+    s.done = 1;
+  } else {
+    s.beta_eff = a.beta;
+    if (a.restart_B2 > 0.0 && static_cast<double>(s.kr) * s.S > a.restart_B2) {
+      s.beta_eff = 0.0;
+      s.kr = 0;
+      s.S = 0.0;
+      s.restarts += 1;
+    }
+    const bool low = s.prec == G_LOW;
+    if (low) {
+      s.it_low += 1;
+      if (rel < s.best_rel) {
+        s.best_rel = rel;
+        s.stall = 0;
+      } else {
+        s.stall += 1;
+      }
+      if (rel < a.switch_tol || s.stall >= a.switch_patience) s.prec = G_FINAL;
+    }
+    if (a.fixed_iters > 0) {
+      if (s.it >= a.fixed_iters) {
+        s.status = IDQ_ST_FIXED;
+        s.done = 1;
+      }
+    } else if (!low && rel < a.tol) {
+      s.status = IDQ_ST_CONVERGED;
+      s.done = 1;
+    } else if (s.it >= a.max_iter) {
+      s.status = IDQ_ST_MAXITER;
+      s.done = 1;
+    }
+    gate = s.prec;
+  }
+  a.st[i] = s;
+  a.gate[i] = s.done ? G_DONE : gate;
+  a.beta_eff[i] = s.beta_eff;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void gather_kernel(const T* b0, const T* b1, T* out,
+                                                      const ImgState* st, long long per) {
+  const int img = blockIdx.y;
+  const size_t base = static_cast<size_t>(img) * per;
+  const T* src = st[img].last_buf == 0 ? b0 : b1;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < per;
+       i += (long long)gridDim.x * kBlock)
+    out[base + i] = src[base + i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dot_stage1(const T* a, const T* b, long long count,
+                                                   double* partials) {
+  double s = 0.0, d1 = 0.0, d2 = 0.0;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < count;
+       i += (long long)gridDim.x * kBlock)
+    s += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+  block_sum3(s, d1, d2);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void sum_stage2(const double* partials, int nblk,
+                                                   double* out, int stride, double scale) {
+  // one block per output: out[blockIdx.x] = scale * sum_j partials[blockIdx.x*stride + j]
+  const double* p = partials + static_cast<size_t>(blockIdx.x) * stride;
+  double s = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int j = threadIdx.x; j < nblk; j += kBlock) s += p[j];
+  block_sum3(s, d1, d2);
+  if (threadIdx.x == 0) out[blockIdx.x] = scale * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void sqnorm_img_stage1(const T* a, long long per,
+                                                          double* partials) {
+  const int img = blockIdx.y;
+  const size_t base = static_cast<size_t>(img) * per;
+  double s = 0.0, d1 = 0.0, d2 = 0.0;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < per;
+       i += (long long)gridDim.x * kBlock) {
+    const double v = static_cast<double>(a[base + i]);
+    s += v * v;
+  }
+  block_sum3(s, d1, d2);
+  if (threadIdx.x == 0) partials[static_cast<size_t>(img) * gridDim.x + blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scale_by_kernel(const T* a, T* out, long long count,
+                                                        const double* scal, int mode) {
+  const double sv = scal[0];
+  const T f = static_cast<T>(mode == 0 ? sv : 1.0 / sqrt(sv));
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < count;
+       i += (long long)gridDim.x * kBlock)
+    out[i] = a[i] * f;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void axpbypcz_kernel(T al, const T* a, T be, const T* b,
+                                                        T ga, const T* c, T* out,
+                                                        long long count) {
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < count;
+       i += (long long)gridDim.x * kBlock) {
+    T v = al * a[i] + be * b[i];
+    if (c) v += ga * c[i];
+    out[i] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient partial sums: each thread owns one weight (or bias) slot and
+// sums over one chunk of the flattened (image, pixel) range.
+// ---------------------------------------------------------------------------
+template <typename TM, typename TS, typename TA>
+__device__ inline TM wg_load(const void* p, int fmt, int ni, int c, int C, int y, int x, int H,
+                             int W) {
+  if (fmt == F_NCHW)
+    return ld<TM>(static_cast<const TS*>(p), ((static_cast<size_t>(ni) * C + c) * H + y) * W + x);
+  return ld<TM>(static_cast<const TA*>(p), ((static_cast<size_t>(ni) * H + y) * W + x) * C + c);
+}
+
+template <typename TM, typename TS, typename TA>
+__global__ __launch_bounds__(kBlock) void wgrad_kernel(WgradArgs a) {
+  const int nw = a.CO * a.CI * 9;
+  const int slot = blockIdx.x * kBlock + threadIdx.x;
+  const int nslots = nw + (a.with_bias ? a.CO : 0);
+  if (slot >= nslots) return;
+  const long long total = static_cast<long long>(a.NI) * a.H * a.W;
+  const long long chunk = (total + a.nchunk - 1) / a.nchunk;
+  const long long lo = blockIdx.y * chunk;
+  const long long hi = lo + chunk < total ? lo + chunk : total;
+  double acc = 0.0;
+  if (slot < nw) {
+    const int co = slot / (a.CI * 9);
+    const int ci = (slot / 9) % a.CI;
+    const int t = slot % 9;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    for (long long q = lo; q < hi; ++q) {
+      const int ni = static_cast<int>(q / (a.H * a.W));
+      const int pix = static_cast<int>(q - static_cast<long long>(ni) * a.H * a.W);
+      const int y = pix / a.W, x = pix - (pix / a.W) * a.W;
+      const int yy = y + dy, xx = x + dx;
+      if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) continue;
+      const TM g = wg_load<TM, TS, TA>(a.g, a.g_fmt, ni, co, a.CO, y, x, a.H, a.W);
+      TM av = wg_load<TM, TS, TA>(a.a0, a.a_fmt, ni, ci, a.CI, yy, xx, a.H, a.W);
+      if (a.a_pro == P_ACT) {
+        av = a.act == IDQ_ACT_SOFTPLUS ? softplus_f(av) : av;
+      } else if (a.a_pro == P_JVP) {
+        const TM hd = wg_load<TM, TS, TA>(a.a1, a.a_fmt, ni, ci, a.CI, yy, xx, a.H, a.W);
+        av = (a.act == IDQ_ACT_SOFTPLUS ? sigmoid_f(av) : TM(1)) * hd;
+      }
+      acc += static_cast<double>(g * av);
+    }
+  } else {
+    const int co = slot - nw;
+    for (long long q = lo; q < hi; ++q) {
+      const int ni = static_cast<int>(q / (a.H * a.W));
+      const int pix = static_cast<int>(q - static_cast<long long>(ni) * a.H * a.W);
+      const int y = pix / a.W, x = pix - (pix / a.W) * a.W;
+      acc += static_cast<double>(wg_load<TM, TS, TA>(a.g, a.g_fmt, ni, co, a.CO, y, x, a.H, a.W));
+    }
+  }
+  a.partials[static_cast<size_t>(blockIdx.y) * nslots + slot] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void reduce_chunks_kernel(const double* partials, int nchunk,
+                                                             int count, double scale, T* out,
+                                                             int accumulate) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partials[static_cast<size_t>(c) * count + i];
+  const double v = scale * s;
+  out[i] = accumulate ? static_cast<T>(static_cast<double>(out[i]) + v) : static_cast<T>(v);
+}
+
+inline int grid_for(long long per) {
+  long long g = (per + kBlock - 1) / kBlock;
+  if (g > 1024) g = 1024;
+  return static_cast<int>(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int launch_stencil(const StencilArgs& a, const double* taps_host, int dtype, hipStream_t s) {
+  if (a.kh > kMaxTap || a.kw > kMaxTap || a.kh % 2 == 0 || a.kw % 2 == 0)
+    return fail(IDQ_E_INVAL, "blur taps must be odd and at most 9x9");
+  if (a.NP > 65535) return fail(IDQ_E_INVAL, "too many planes");
+  if (a.NP == 0) return IDQ_OK;
+  return dtype == IDQ_F64 ? stencil_dispatch<double>(a, taps_host, s)
+                          : stencil_dispatch<float>(a, taps_host, s);
+}
+
+int launch_extrap(const void* x, const void* xp, void* z, const double* beta_eff,
+                  const int* gate, int n, long long per, int dtype, hipStream_t s) {
+  dim3 grid(grid_for(per), n);
+  if (dtype == IDQ_F64)
+    extrap_kernel<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(x),
+                                                  static_cast<const double*>(xp),
+                                                  static_cast<double*>(z), beta_eff, gate, per);
+  else
+    extrap_kernel<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(x),
+                                                 static_cast<const float*>(xp),
+                                                 static_cast<float*>(z), beta_eff, gate, per);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_update(const UpdateArgs& a, int dtype, hipStream_t s) {
+  dim3 grid(a.nblk, a.n);
+  if (dtype == IDQ_F64)
+    update_kernel<double><<<grid, kBlock, 0, s>>>(a);
+  else
+    update_kernel<float><<<grid, kBlock, 0, s>>>(a);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+  finalize_kernel<<<(a.n + 63) / 64, 64, 0, s>>>(a);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_gather_result(const void* b0, const void* b1, void* out, const ImgState* st, int n,
+                         long long per, int dtype, hipStream_t s) {
+  dim3 grid(grid_for(per), n);
+  if (dtype == IDQ_F64)
+    gather_kernel<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(b0),
+                                                  static_cast<const double*>(b1),
+                                                  static_cast<double*>(out), st, per);
+  else
+    gather_kernel<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(b0),
+                                                 static_cast<const float*>(b1),
+                                                 static_cast<float*>(out), st, per);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_dot(const void* a, const void* b, long long count, int dtype, double* partials,
+               int nblk, double* out, hipStream_t s) {
+  if (dtype == IDQ_F64)
+    dot_stage1<double><<<nblk, kBlock, 0, s>>>(static_cast<const double*>(a),
+                                               static_cast<const double*>(b), count, partials);
+  else
+    dot_stage1<float><<<nblk, kBlock, 0, s>>>(static_cast<const float*>(a),
+                                              static_cast<const float*>(b), count, partials);
+  sum_stage2<<<1, kBlock, 0, s>>>(partials, nblk, out, nblk, 1.0);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_half_sqnorm_per_image(const void* a, int n, long long per, int dtype,
+                                 double* partials, int nblk, double* out, hipStream_t s) {
+  dim3 grid(nblk, n);
+  if (dtype == IDQ_F64)
+    sqnorm_img_stage1<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(a), per, partials);
+  else
+    sqnorm_img_stage1<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(a), per, partials);
+  sum_stage2<<<n, kBlock, 0, s>>>(partials, nblk, out, nblk, 0.5);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_scale_by(const void* a, void* out, long long count, const double* scal, int mode,
+                    int dtype, hipStream_t s) {
+  const int g = grid_for(count);
+  if (dtype == IDQ_F64)
+    scale_by_kernel<double><<<g, kBlock, 0, s>>>(static_cast<const double*>(a),
+                                                 static_cast<double*>(out), count, scal, mode);
+  else
+    scale_by_kernel<float><<<g, kBlock, 0, s>>>(static_cast<const float*>(a),
+                                                static_cast<float*>(out), count, scal, mode);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_axpbypcz(double alpha, const void* a, double beta, const void* b, double gamma,
+                    const void* c, void* out, long long count, int dtype, hipStream_t s) {
+  const int g = grid_for(count);
+  if (dtype == IDQ_F64)
+    axpbypcz_kernel<double><<<g, kBlock, 0, s>>>(alpha, static_cast<const double*>(a), beta,
+                                                 static_cast<const double*>(b), gamma,
+                                                 static_cast<const double*>(c),
+                                                 static_cast<double*>(out), count);
+  else
+    axpbypcz_kernel<float><<<g, kBlock, 0, s>>>(
+        static_cast<float>(alpha), static_cast<const float*>(a), static_cast<float>(beta),
+        static_cast<const float*>(b), static_cast<float>(gamma), static_cast<const float*>(c),
+        static_cast<float*>(out), count);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_wgrad(const WgradArgs& a, int prec, hipStream_t s) {
+  const int nslots = a.CO * a.CI * 9 + (a.with_bias ? a.CO : 0);
+  dim3 grid((nslots + kBlock - 1) / kBlock, a.nchunk);
+  if (prec == PREC_F64)
+    wgrad_kernel<double, double, double><<<grid, kBlock, 0, s>>>(a);
+  else if (prec == PREC_F32)
+    wgrad_kernel<float, float, float><<<grid, kBlock, 0, s>>>(a);
+  else
+    wgrad_kernel<float, float, bf16><<<grid, kBlock, 0, s>>>(a);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_reduce_chunks(const double* partials, int nchunk, int count, double scale, void* out,
+                         int accumulate, int dtype, hipStream_t s) {
+  const int g = (count + kBlock - 1) / kBlock;
+  if (dtype == IDQ_F64)
+    reduce_chunks_kernel<double><<<g, kBlock, 0, s>>>(partials, nchunk, count, scale,
+                                                      static_cast<double*>(out), accumulate);
+  else
+    reduce_chunks_kernel<float><<<g, kBlock, 0, s>>>(partials, nchunk, count, scale,
+                                                     static_cast<float*>(out), accumulate);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+}  // namespace idq

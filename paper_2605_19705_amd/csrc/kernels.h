@@ -1,0 +1,174 @@
+// Kernel launch interfaces used by the host drivers (api.hip, ws.hip).
+#pragma once
+
+#include "common.h"
+
+namespace idq {
+
+// Arithmetic of a conv pass: storage and math types.
+//   PREC_F64 : double everywhere
+//   PREC_F32 : float everywhere
+//   PREC_BF16: float state tensors, bfloat16 activations and operands,
+//              float accumulation
+enum Prec { PREC_F64 = IDQ_F64, PREC_F32 = IDQ_F32, PREC_BF16 = IDQ_BF16 };
+
+// Input transform applied while loading a conv operand.
+enum Pro {
+  P_NONE = 0,  // a = in0
+  P_ACT = 1,   // a = sigma(in0)                  (in0 = pre-activation h)
+  P_JVP = 2,   // a = sigma'(in0) * in1           (in0 = h, in1 = tangent h')
+};
+
+// Output transform of a conv pass (acc = sum over taps and input channels).
+enum Epi {
+  E_STORE = 0,  // out0 = acc + b
+  E_RES = 1,    // out0 = e0 - (acc + b)                   (r = x - N(x))
+  E_DELTA = 2,  // out0 = sigma'(e0) * acc                 (backprop through sigma)
+  E_SUB = 3,    // out0 = e0 - acc                         (grad g = r - J^T r)
+  E_RAW = 4,    // out0 = acc
+  E_DDOT = 5,   // out0 = sigma''(e0) e1 e2 + sigma'(e0) acc, out1 = sigma'(e0) e2
+};
+
+enum Fmt { F_NCHW = 0, F_NHWC = 1 };
+
+// One zero-padded 3x3 conv pass over NI images of H x W pixels.
+// Weights `wgt` point at the layer's packed weights for the kernel family
+// chosen by the launcher (see conv_weights_layout in api.hip).
+struct ConvArgs {
+  int NI, H, W, CI, CO;
+  int in_fmt, out_fmt;
+  int pro, epi, act;
+  const void* in0;
+  const void* in1;
+  const void* wgt;      // direct: [co][ci][9] of the math type
+  const void* wmfma;    // MFMA-packed weights (nullable)
+  const void* bias;     // [co] of the math type (nullable => 0)
+  void* out0;
+  void* out1;
+  const void* e0;
+  const void* e1;
+  const void* e2;
+  const int* gate;      // per solver image phase gate (nullable => always run)
+  int gate_mask;        // run image i iff (1 << gate[i]) & gate_mask
+  int img_div;          // solver image = net image / img_div
+};
+
+// Phase gate values written by the finalize kernel.
+enum Gate { G_DONE = 0, G_LOW = 1, G_FINAL = 2 };
+constexpr int GM_ACTIVE = (1 << G_LOW) | (1 << G_FINAL);
+
+__device__ inline bool gate_open(const int* gate, int mask, int img) {
+  return gate == nullptr || ((1 << gate[img]) & mask) != 0;
+}
+
+int launch_conv(const ConvArgs& a, int prec, hipStream_t s);
+
+// MFMA weight packing for a layer; returns bytes needed when dst == nullptr.
+size_t pack_mfma_weights(int prec, int ci, int co, const double* w /*[co][ci][9]*/,
+                         void* dst_host);
+bool mfma_supported(int prec, int ci, int co);
+
+// ---- stencils of the forward operator (circular, per plane) --------------
+enum StencilMode {
+  S_B = 0,          // out = B in0
+  S_BT = 1,         // out = B^T in0
+  S_B_MINUS = 2,    // out = B in0 - aux                          (A z - y)
+  S_TANH_A = 3,     // out = tanh(g B in0) / tanh g
+  S_TANH_WRES = 4,  // t = tanh(g B in0): out = c1 (1 - t^2) (t / tanh g - aux)
+  S_TANH_JTW = 5,   // t = tanh(g B in0): out = c1 (1 - t^2) aux
+  S_TANH_HESS = 6,  // t = tanh(g B in0), u = B in1:
+                    //   out = u (c1^2 (1-t^2)^2 + (t/tanh g - aux) curv(t))
+};
+
+struct StencilArgs {
+  int NP, H, W;             // planes (n * c), spatial
+  int kh, kw;
+  double gain;
+  const void* in0;
+  const void* in1;
+  const void* aux;
+  void* out;
+  const int* gate;          // per solver image (nullable => always run)
+  int plane_div;            // solver image = plane / plane_div
+  int mode;
+};
+int launch_stencil(const StencilArgs& a, const double* taps_host, int dtype, hipStream_t s);
+
+// ---- elementwise / reductions ---------------------------------------------
+// z = x + beta_eff[img] * (x - xp) over n images of `per` elements.
+int launch_extrap(const void* x, const void* xp, void* z, const double* beta_eff,
+                  const int* gate, int n, long long per, int dtype, hipStream_t s);
+
+// Fused update of the i-DEQ step and per-block float64 partial sums:
+//   xn = z - tau (gf + lambda q),  gf = (gf_is_point ? p - y : gf)
+//   partials[img][blk] = { sum (xn - x)^2, sum x^2, nonfinite count }
+struct UpdateArgs {
+  int n;
+  long long per;
+  const void* x;
+  const void* z;
+  const void* gf;      // grad f, or nullptr when gf = p - y (identity A)
+  const void* p;       // gradient point (identity A)
+  const void* y;
+  const void* q;       // grad g (nullable => 0)
+  void* xn;
+  double tau, lambda;
+  const int* gate;
+  double* partials;    // [n][nblk][3]
+  int nblk;
+};
+int launch_update(const UpdateArgs& a, int dtype, hipStream_t s);
+
+// Per-image bookkeeping after an update (restart, stop, precision phase).
+struct ImgState {
+  int it, kr, status, done;
+  int prec, it_low, stall, restarts;
+  int last_buf, pad0, pad1, pad2;
+  double S, rel, best_rel, beta_eff;
+};
+struct FinalizeArgs {
+  int n, nblk;
+  const double* partials;
+  ImgState* st;
+  int* gate;
+  double* beta_eff;
+  double beta, tol, restart_B2, switch_tol;
+  int max_iter, fixed_iters, switch_patience;
+  int buf_index;        // ping-pong buffer holding the new iterate
+};
+int launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// x_out[img] = bufs[st[img].last_buf][img]
+int launch_gather_result(const void* b0, const void* b1, void* out, const ImgState* st,
+                         int n, long long per, int dtype, hipStream_t s);
+
+// Batch float64 dot product <a, b> (deterministic two-stage); result in *out.
+int launch_dot(const void* a, const void* b, long long count, int dtype, double* partials,
+               int nblk, double* out, hipStream_t s);
+// Per-image 0.5 * sum a^2 into out[img].
+int launch_half_sqnorm_per_image(const void* a, int n, long long per, int dtype,
+                                 double* partials, int nblk, double* out, hipStream_t s);
+// out = a * scale[0] ^ {pow}  (pow = -1/2 => divide by sqrt)  ; generic axpby
+int launch_scale_by(const void* a, void* out, long long count, const double* scal,
+                    int mode, int dtype, hipStream_t s);
+// out = alpha * a + beta * b + gamma * c (c nullable)
+int launch_axpbypcz(double alpha, const void* a, double beta, const void* b, double gamma,
+                    const void* c, void* out, long long count, int dtype, hipStream_t s);
+
+// ---- weight gradient:  dW[co][ci][tap] += scale * sum_p G[p][co] A[p+off][ci] ---
+struct WgradArgs {
+  int NI, H, W, CI, CO;
+  int g_fmt, a_fmt;
+  int a_pro, act;          // P_NONE | P_ACT | P_JVP on the A operand
+  const void* g;           // gradient operand (c_out channels)
+  const void* a0;          // A operand (c_in channels)
+  const void* a1;          // tangent for P_JVP
+  double* partials;        // [nchunk][CO*CI*9 + CO]
+  int nchunk;
+  int with_bias;           // also sum G over pixels into the bias slots
+};
+int launch_wgrad(const WgradArgs& a, int prec, hipStream_t s);
+// out[i] (+)= scale * sum_chunk partials[chunk][i]; out of dtype, i < count
+int launch_reduce_chunks(const double* partials, int nchunk, int count, double scale,
+                         void* out, int accumulate, int dtype, hipStream_t s);
+
+}  // namespace idq
