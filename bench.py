@@ -1,0 +1,211 @@
+#!/usr/bin/env python
+"""Throughput of the i-DEQ forward pass on one MI355X.
+
+Workload (deblurring): a batch of 8 synthetic 3x256x256 images, circular 9x9
+Gaussian blur (sigma 1.6) plus noise of std 0.01, regularizer
+g(x) = 1/2 ||x - N(x)||^2 with N a 5-layer 3->64->64->64->64->3 SoftPlus conv
+net (He-normal, seed 0), lambda 1, beta 0.5, tau = 0.9 / L with L from 30
+power iterations at the measurements (computed once, outside the timed region).
+One step = one i-DEQ solve of the whole batch until every image reaches
+||x^{k+1} - x^k|| / ||x^k|| < 1e-4.
+
+Two arms are timed:
+  headline  bf16 matrix-core convs (fp32 accumulate) until rel < 1e-3 or
+            stagnation, then fp32 refinement to 1e-4, started from the learned
+            warm start when its weights are available (else from y),
+  fp32      fp32 matrix-core convs from x0 = y ("FP32 plain").
+Prints one JSON line (value = headline images/s).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "restored 256^2 images/s at rel. residual 1e-4: BF16+warm-start vs FP32 plain"
+BF16_PEAK = 2.5e15     # MI355X dense bf16 matrix-core peak, FLOP/s
+F32_PEAK = 157.3e12    # MI355X dense fp32 matrix-core peak, FLOP/s
+FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_problem(torch, n=8, h=256, w=256):
+    import synth
+    from paper_2605_19705_amd import IDQ
+    layers = synth.he_normal_net(synth.net_channels("rgb64"), 0)
+    taps = synth.gaussian_taps(9, 1.6)
+    ctx = IDQ(layers, op_kind="blur", taps=taps, device=0)
+    xt, nz = synth.make_batch(2, n, 3, h, w)
+    dev = torch.device("cuda:0")
+    xt_g = torch.from_numpy(xt).float().to(dev)
+    nz_g = torch.from_numpy(nz).float().to(dev)
+    y = ctx.apply_A(xt_g) + 0.01 * nz_g
+    return ctx, y.contiguous(), layers, taps, xt, nz
+
+
+def time_arm(torch, ctx, y, K, W, profile=False, **kw):
+    for _ in range(W):
+        ctx.solve(y, **kw)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile(True)
+    times, iters, low = [], [], []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(K):
+        t0 = time.perf_counter()
+        x, res = ctx.solve(y, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(res.iters.tolist())
+        low.append(res.iters_low.tolist())
+        assert (res.status == 0).all(), f"solve did not converge: {res.status}"
+    total = time.perf_counter() - t_all
+    prof = ctx.profile_read() if profile else None
+    if profile:
+        ctx.profile(False)
+    return dict(total_s=total, step_s=times, iters=iters, iters_low=low, prof=prof, x=x)
+
+
+def cpu_baseline(iters_per_image, sample_iters=3):
+    """The float64 oracle on the host: one 256x256 image of the same batch,
+    `sample_iters` i-DEQ iterations timed, scaled by the GPU fp32 arm's mean
+    iteration count to images per second."""
+    import numpy as np
+    import synth
+    from oracle import operators as O, regularizer as R, solver as S
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    layers = synth.he_normal_net(synth.net_channels("rgb64"), 0)
+    op = O.Operator("blur", synth.gaussian_taps(9, 1.6))
+    xt, nz = synth.make_batch(2, 1, 3, 256, 256)
+    y = op.A(xt) + 0.01 * nz
+    P = S.Problem(op, R.Net(layers), 1.0)
+    t0 = time.perf_counter()
+    S.ideq_solve(P, y, y, 0.5, 0.15, fixed_iters=sample_iters)
+    dt = time.perf_counter() - t0
+    t_iter = dt / sample_iters
+    return {"value": 1.0 / (t_iter * iters_per_image), "unit": "images/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"1 of the 8 images, {sample_iters} float64 i-DEQ iterations "
+                      f"({t_iter:.2f} s per image-iteration), scaled by the fp32 arm's "
+                      f"{iters_per_image:.1f} iterations per image"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-plain arm")
+    ap.add_argument("--ws-weights", default=None, help="warm-start weights (.npy, float64)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the per-image solves need no exchange, so more "
+              "GPUs would run independent shares of the batch; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+
+    log("bench: building the deblurring problem (8x3x256x256)")
+    ctx, y, layers, taps, xt, nz = make_problem(torch)
+    v0 = torch.from_numpy(synth.random_field(12345, tuple(y.shape))).float().to(y.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = ctx.lipschitz(y, y, v0, lam=1.0, iters=30, conv_prec="f32")
+    t_L = time.perf_counter() - t0
+    tau = 0.9 / L
+    log(f"bench: L = {L:.6f}, tau = {tau:.6f} ({t_L * 1e3:.1f} ms, outside the timed region)")
+
+    common = dict(beta=0.5, tau=tau, lam=1.0, tol=1e-4, max_iter=2000)
+    ws = None
+    init = "y"
+    if args.ws_weights and os.path.exists(args.ws_weights):
+        from paper_2605_19705_amd import WarmStart
+        ws = WarmStart(np.load(args.ws_weights), device=0)
+        init = "warmstart"
+    head_kw = dict(common, conv_prec="bf16", switch_tol=1e-3, switch_patience=10, init=init, ws=ws)
+
+    log(f"bench: headline arm (bf16 + fp32 refinement, init={init}), "
+        f"{args.warmup} warmup + {args.steps} timed solves")
+    head = time_arm(torch, ctx, y, args.steps, args.warmup, profile=True, **head_kw)
+    n_img = y.shape[0]
+    value = n_img * args.steps / head["total_s"]
+    log(f"bench: headline {value:.2f} images/s, iterations {head['iters'][-1]}, "
+        f"bf16 part {head['iters_low'][-1]}")
+
+    fp32 = None
+    if not args.no_fp32:
+        log("bench: fp32-plain arm")
+        fp32 = time_arm(torch, ctx, y, max(1, min(args.steps, 2)), 0, profile=False,
+                        conv_prec="f32", **common)
+        fp32["value"] = n_img * len(fp32["step_s"]) / fp32["total_s"]
+        log(f"bench: fp32 plain {fp32['value']:.2f} images/s, iterations {fp32['iters'][-1]}")
+
+    # roofline of the dominant kernel: the 64->64 bf16 conv passes of the timed solves
+    ms, launches, px = head["prof"]["conv64_bf16"]
+    avg_ms = ms / max(launches, 1)
+    flops_per_launch = FLOP_PER_PX_64 * px / max(launches, 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) if launches else 0.0
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "traffic": None,
+                "kernel": "conv_mfma_kernel<bf16, 64, 64>", "launches": launches,
+                "avg_launch_us": avg_ms * 1e3,
+                "flop_per_launch": flops_per_launch}
+    phases = {k: {"ms": v[0], "launches": v[1]} for k, v in head["prof"].items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        ref_iters = float(np.mean(fp32["iters"][-1])) if fp32 else float(np.mean(head["iters"][-1]))
+        log("bench: cpu baseline (float64 oracle on the host)")
+        cpu = cpu_baseline(ref_iters)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * head["total_s"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "i-DEQ deblurring, 8x3x256x256, circular 9x9 gaussian (sigma 1.6), "
+                        "noise 0.01, 5-layer 64-channel softplus regularizer, rel. residual 1e-4",
+            "arm": f"bf16 convs + fp32 refinement, init={init}",
+            "global_batch": n_img,
+            "parallelism": "single GPU",
+        },
+        "iters_per_image": head["iters"][-1],
+        "bf16_iters_per_image": head["iters_low"][-1],
+        "fp32_plain": None if fp32 is None else {
+            "value": fp32["value"], "iters_per_image": fp32["iters"][-1],
+            "ms_per_step": 1e3 * fp32["total_s"] / len(fp32["step_s"])},
+        "speedup_vs_fp32_plain": None if fp32 is None else value / fp32["value"],
+        "step_size": {"L": L, "tau": tau, "power_iteration_ms": t_L * 1e3},
+        "device_ms_by_class": phases,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -208,6 +208,24 @@ int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_d
                  void* dtheta, double* dlambda, int n, int c, int h, int w, int dtype,
                  const idq_bwd_opts* opts, idq_bwd_info* info, void* stream);
 
+/* ---- device-time accounting ------------------------------------------------
+ * When enabled, the library brackets its kernel launches with HIP events on
+ * the launch stream and counts the output pixels each conv pass computed
+ * (images frozen by the stopping rule are skipped, so only done work counts).
+ * Classes: */
+#define IDQ_PROF_CONV64_BF16   0   /* 64->64-channel conv passes, bf16 MFMA     */
+#define IDQ_PROF_CONV64_F32    1   /* 64->64-channel conv passes, fp32 MFMA     */
+#define IDQ_PROF_CONV_OTHER    2   /* every other conv pass                      */
+#define IDQ_PROF_STENCIL       3   /* blur stencils of grad f                    */
+#define IDQ_PROF_UPDATE        4   /* extrapolation, update, finalize            */
+#define IDQ_PROF_WARMSTART     5   /* warm-start network inference               */
+/* Enable (on != 0) or disable accounting; resets all counters.  Synchronous. */
+int idq_profile_enable(idq_ctx* ctx, int on);
+/* Totals since the last enable: summed device time (ms), number of launches
+ * and output pixels computed (conv classes; 0 otherwise).  Synchronous. */
+int idq_profile_read(idq_ctx* ctx, int cls, double* total_ms, long long* launches,
+                     double* pixels);
+
 /* ---- learned warm start x0 = y + W_phi(y) ---------------------------------
  * 2-level encoder-decoder on 3-channel images (h, w even):
  *   3->32->32 | avgpool 2x2 | 32->64->64->64->64 | nearest upsample |

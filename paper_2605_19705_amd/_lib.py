@@ -21,11 +21,14 @@ IDQ_INIT_Y, IDQ_INIT_ZERO, IDQ_INIT_WARMSTART = 0, 1, 2
 IDQ_MAX_LAYERS = 8
 IDQ_ST_CONVERGED, IDQ_ST_MAXITER, IDQ_ST_FIXED, IDQ_ST_NONFINITE = 0, 1, 2, -4
 IDQ_BWD_JFB, IDQ_BWD_IMPLICIT = 0, 1
+PROF_CLASSES = {"conv64_bf16": 0, "conv64_f32": 1, "conv_other": 2, "stencil": 3, "update": 4,
+                "warmstart": 5}
 
 EXPORTED = [
     "idq_last_error", "idq_version", "idq_solve_opts_default", "idq_create", "idq_destroy",
     "idq_set_params", "idq_num_params", "idq_apply_A", "idq_apply_AT", "idq_grad_data",
     "idq_grad_reg", "idq_hvp", "idq_lipschitz", "idq_solve", "idq_backward",
+    "idq_profile_enable", "idq_profile_read",
     "idq_ws_create", "idq_ws_destroy", "idq_ws_num_params", "idq_ws_get_params",
     "idq_ws_set_params", "idq_ws_forward", "idq_ws_train_step", "idq_ws_grad",
 ]
@@ -87,6 +90,8 @@ _SIGS = {
                    C.POINTER(SolveInfo), vp], ip),
     "idq_backward": ([vp, vp, vp, vp, vp, dp, ip, ip, ip, ip, ip, C.POINTER(BwdOpts),
                       C.POINTER(BwdInfo), vp], ip),
+    "idq_profile_enable": ([vp, ip], ip),
+    "idq_profile_read": ([vp, ip, dp, C.POINTER(C.c_longlong), dp], ip),
     "idq_ws_create": ([C.POINTER(vp), dp, C.c_longlong, ip], ip),
     "idq_ws_destroy": ([vp], ip),
     "idq_ws_num_params": ([], C.c_longlong),

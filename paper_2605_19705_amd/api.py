@@ -123,6 +123,19 @@ class IDQ:
         L.check(L.lib().idq_set_params(self._h, flat.ctypes.data_as(C.POINTER(C.c_double)),
                                        flat.size))
 
+    # ---- device-time accounting ---------------------------------------------------
+    def profile(self, on=True):
+        L.check(L.lib().idq_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self):
+        """{class: (total_ms, launches, pixels)} since the last profile(True)."""
+        out = {}
+        for name, cls in L.PROF_CLASSES.items():
+            ms, n, px = C.c_double(), C.c_longlong(), C.c_double()
+            L.check(L.lib().idq_profile_read(self._h, cls, C.byref(ms), C.byref(n), C.byref(px)))
+            out[name] = (ms.value, n.value, px.value)
+        return out
+
     # ---- operators -------------------------------------------------------------
     def apply_A(self, x):
         out = torch.empty_like(x)

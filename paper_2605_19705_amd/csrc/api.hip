@@ -48,7 +48,71 @@ void Workspace::release() {
   }
 }
 
+int Profiler::begin(int cls, hipStream_t s, ProfRec* r) {
+  r->cls = cls;
+  for (hipEvent_t* e : {&r->e0, &r->e1}) {
+    if (!pool.empty()) {
+      *e = pool.back();
+      pool.pop_back();
+    } else {
+      IDQ_HIP(hipEventCreate(e));
+    }
+  }
+  IDQ_HIP(hipEventRecord(r->e0, s));
+  return IDQ_OK;
+}
+
+int Profiler::end(ProfRec& r, hipStream_t s) {
+  IDQ_HIP(hipEventRecord(r.e1, s));
+  pending.push_back(r);
+  return IDQ_OK;
+}
+
+int Profiler::flush() {
+  for (ProfRec& r : pending) {
+    IDQ_HIP(hipEventSynchronize(r.e1));
+    float t = 0.f;
+    IDQ_HIP(hipEventElapsedTime(&t, r.e0, r.e1));
+    ms[r.cls] += t;
+    launches[r.cls] += 1;
+    pool.push_back(r.e0);
+    pool.push_back(r.e1);
+  }
+  pending.clear();
+  return IDQ_OK;
+}
+
+void Profiler::release() {
+  flush();
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+  pool.clear();
+  if (dev_px) hipFree(dev_px);
+  dev_px = nullptr;
+}
+
 namespace {
+
+// Launch a conv pass, with device-time accounting when profiling is on.
+int run_conv(idq_ctx* ctx, ConvArgs a, int prec, hipStream_t s) {
+  if (!ctx->prof.on) return launch_conv(a, prec, s);
+  int cls = PC_CONV_OTHER;
+  if (a.CI == 64 && a.CO == 64 && prec != PREC_F64)
+    cls = prec == PREC_BF16 ? PC_CONV_WIDE_BF16 : PC_CONV_WIDE_F32;
+  a.work_px = ctx->prof.dev_px + cls;
+  ProfRec r;
+  IDQ_TRY(ctx->prof.begin(cls, s, &r));
+  IDQ_TRY(launch_conv(a, prec, s));
+  return ctx->prof.end(r, s);
+}
+
+template <class F>
+int profiled(idq_ctx* ctx, int cls, hipStream_t s, F&& f) {
+  if (!ctx->prof.on) return f();
+  ProfRec r;
+  IDQ_TRY(ctx->prof.begin(cls, s, &r));
+  IDQ_TRY(f());
+  return ctx->prof.end(r, s);
+}
 
 size_t math_size(int prec) { return prec == PREC_F64 ? 8 : 4; }
 size_t act_size(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
@@ -187,7 +251,8 @@ ConvArgs conv_base(const idq_ctx* ctx, const Geometry& g, int l, bool transposed
 // Regularizer passes
 // ---------------------------------------------------------------------------
 
-// Forward pass of N at p (state tensor): stores h_1..h_{L-1} and r = p - N(p).
+// Forward pass of N at p (state tensor): stores a_l = sigma(h_l) (l < L) and
+// r = p - N(p).
 int net_forward(idq_ctx* ctx, const Geometry& g, int prec, const void* p, void* r,
                 const int* gate, int mask, hipStream_t s) {
   const int L = ctx->L;
@@ -197,7 +262,7 @@ int net_forward(idq_ctx* ctx, const Geometry& g, int prec, const void* p, void* 
     ConvArgs a = conv_base(ctx, g, l, false, prec, gate, mask);
     a.in0 = prev;
     a.in_fmt = l == 0 ? F_NCHW : F_NHWC;
-    a.pro = l == 0 ? P_NONE : P_ACT;
+    a.pro = P_NONE;
     if (l == L - 1) {
       a.out_fmt = F_NCHW;
       a.epi = E_RES;
@@ -207,11 +272,11 @@ int net_forward(idq_ctx* ctx, const Geometry& g, int prec, const void* p, void* 
       void* h;
       IDQ_TRY(ctx->ws.get(W_H0 + l, abytes, &h));
       a.out_fmt = F_NHWC;
-      a.epi = E_STORE;
+      a.epi = E_ACT;
       a.out0 = h;
       prev = h;
     }
-    IDQ_TRY(launch_conv(a, prec, s));
+    IDQ_TRY(run_conv(ctx, a, prec, s));
   }
   return IDQ_OK;
 }
@@ -249,7 +314,7 @@ int net_grad(idq_ctx* ctx, const Geometry& g, int prec, const void* p, void* q,
       a.out0 = o;
       din = o;
     }
-    IDQ_TRY(launch_conv(a, prec, s));
+    IDQ_TRY(run_conv(ctx, a, prec, s));
   }
   return IDQ_OK;
 }
@@ -297,7 +362,7 @@ int net_hvp(idq_ctx* ctx, const Geometry& g, int prec, const void* x, const void
       prev_h = h;
       prev_hd = hd;
     }
-    IDQ_TRY(launch_conv(a, prec, s));
+    IDQ_TRY(run_conv(ctx, a, prec, s));
   }
   // reverse pass for (delta, delta')
   const void* din = r;
@@ -312,7 +377,7 @@ int net_hvp(idq_ctx* ctx, const Geometry& g, int prec, const void* x, const void
       a.epi = E_SUB;
       a.e0 = rd;
       a.out0 = Hw;
-      IDQ_TRY(launch_conv(a, prec, s));
+      IDQ_TRY(run_conv(ctx, a, prec, s));
       break;
     }
     void *h, *hd, *dl, *ddl;
@@ -327,7 +392,7 @@ int net_hvp(idq_ctx* ctx, const Geometry& g, int prec, const void* x, const void
     a.out_fmt = F_NHWC;
     a.epi = E_RAW;
     a.out0 = t;
-    IDQ_TRY(launch_conv(a, prec, s));
+    IDQ_TRY(run_conv(ctx, a, prec, s));
     ConvArgs b = a;
     b.in0 = ddin;
     b.epi = E_DDOT;
@@ -336,7 +401,7 @@ int net_hvp(idq_ctx* ctx, const Geometry& g, int prec, const void* x, const void
     b.e2 = t;
     b.out0 = ddl;
     b.out1 = dl;
-    IDQ_TRY(launch_conv(b, prec, s));
+    IDQ_TRY(run_conv(ctx, b, prec, s));
     din = dl;
     ddin = ddl;
   }
@@ -380,12 +445,12 @@ int data_grad(idq_ctx* ctx, const Geometry& g, int dtype, const void* p, const v
   a.aux = y;
   a.out = tmp;
   a.mode = ctx->op_kind == IDQ_OP_BLUR_CIRC ? S_B_MINUS : S_TANH_WRES;
-  IDQ_TRY(launch_stencil(a, ctx->taps.data(), dtype, s));
+  IDQ_TRY(profiled(ctx, PC_STENCIL, s, [&] { return launch_stencil(a, ctx->taps.data(), dtype, s); }));
   StencilArgs b = stencil_base(ctx, g, gate);
   b.in0 = tmp;
   b.out = gf;
   b.mode = S_BT;
-  return launch_stencil(b, ctx->taps.data(), dtype, s);
+  return profiled(ctx, PC_STENCIL, s, [&] { return launch_stencil(b, ctx->taps.data(), dtype, s); });
 }
 
 // Hessian of f at (x, y) along v into out.
@@ -568,7 +633,9 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     for (; t < t_end; ++t) {
       void* xa = xb[t % 2];
       void* xp = xb[(t + 1) % 2];
-      IDQ_TRY(launch_extrap(xa, xp, z, static_cast<const double*>(beta), gp, n, g.per, dtype, s));
+      IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
+        return launch_extrap(xa, xp, z, static_cast<const double*>(beta), gp, n, g.per, dtype, s);
+      }));
       const void* p = o->grad_at == IDQ_GRAD_AT_CURRENT ? xa : z;
       if (!identity) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false));
       if (use_net) {
@@ -590,12 +657,15 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
       ua.gate = gp;
       ua.partials = static_cast<double*>(part);
       ua.nblk = nblk;
-      IDQ_TRY(launch_update(ua, dtype, s));
       fa.buf_index = (t + 1) % 2;
-      IDQ_TRY(launch_finalize(fa, s));
+      IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
+        IDQ_TRY(launch_update(ua, dtype, s));
+        return launch_finalize(fa, s);
+      }));
     }
     IDQ_HIP(hipMemcpyAsync(ctx->host_gate, gate, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     IDQ_HIP(hipStreamSynchronize(s));
+    if (ctx->prof.on) IDQ_TRY(ctx->prof.flush());
     bool any = false, anylow = false;
     for (int i = 0; i < n; ++i) {
       any |= ctx->host_gate[i] != G_DONE;
@@ -716,7 +786,7 @@ int backward_impl(idq_ctx* ctx, const void* xbar, const void* y, const void* v, 
       wa.a0 = xbar;
     } else {
       wa.a_fmt = F_NHWC;
-      wa.a_pro = P_ACT;
+      wa.a_pro = P_NONE;
       wa.a0 = hprev;
     }
     wa.with_bias = 1;
@@ -877,10 +947,45 @@ int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, in
   });
 }
 
+int idq_profile_enable(idq_ctx* ctx, int on) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(IDQ_E_INVAL, "null context");
+    IDQ_TRY(set_device(ctx));
+    IDQ_HIP(hipDeviceSynchronize());
+    IDQ_TRY(ctx->prof.flush());
+    if (!ctx->prof.dev_px) IDQ_HIP(hipMalloc(&ctx->prof.dev_px, sizeof(unsigned long long) * PC_COUNT));
+    IDQ_HIP(hipMemset(ctx->prof.dev_px, 0, sizeof(unsigned long long) * PC_COUNT));
+    for (int i = 0; i < PC_COUNT; ++i) {
+      ctx->prof.ms[i] = 0.0;
+      ctx->prof.launches[i] = 0;
+    }
+    ctx->prof.on = on != 0;
+    return IDQ_OK;
+  });
+}
+
+int idq_profile_read(idq_ctx* ctx, int cls, double* total_ms, long long* launches,
+                     double* pixels) {
+  return guarded([&]() -> int {
+    if (!ctx || cls < 0 || cls >= PC_COUNT) return fail(IDQ_E_INVAL, "bad profile class");
+    IDQ_TRY(set_device(ctx));
+    IDQ_HIP(hipDeviceSynchronize());
+    IDQ_TRY(ctx->prof.flush());
+    unsigned long long px = 0;
+    if (ctx->prof.dev_px)
+      IDQ_HIP(hipMemcpy(&px, ctx->prof.dev_px + cls, sizeof(px), hipMemcpyDeviceToHost));
+    if (total_ms) *total_ms = ctx->prof.ms[cls];
+    if (launches) *launches = ctx->prof.launches[cls];
+    if (pixels) *pixels = static_cast<double>(px);
+    return IDQ_OK;
+  });
+}
+
 int idq_destroy(idq_ctx* ctx) {
   if (!ctx) return IDQ_OK;
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
+  ctx->prof.release();
   free_layers(ctx);
   ctx->ws.release();
   if (ctx->host_gate) hipHostFree(ctx->host_gate);

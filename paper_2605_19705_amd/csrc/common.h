@@ -64,17 +64,14 @@ __device__ inline double sigmoid_f(double t) {
   return t >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
 }
 
-template <int ACT, typename T>
-__device__ inline T act_fn(T t) { return ACT == IDQ_ACT_SOFTPLUS ? softplus_f(t) : t; }
-template <int ACT, typename T>
-__device__ inline T dact_fn(T t) { return ACT == IDQ_ACT_SOFTPLUS ? sigmoid_f(t) : T(1); }
-template <int ACT, typename T>
-__device__ inline T d2act_fn(T t) {
-  if (ACT == IDQ_ACT_SOFTPLUS) {
-    T s = sigmoid_f(t);
-    return s * (T(1) - s);
-  }
-  return T(0);
+// sigma'(h) and sigma''(h) recovered from a = softplus(h):
+// sigma(h) = 1 - exp(-softplus(h)) = -expm1(-a).
+__device__ inline float dsp_from_a(float a) { return -expm1f(-a); }
+__device__ inline double dsp_from_a(double a) { return -expm1(-a); }
+// Fast variant for bfloat16 passes (operands carry 8 significant bits).
+__device__ inline float dsp_from_a_fast(float a) { return 1.f - __expf(-a); }
+__device__ inline float softplus_fast(float t) {
+  return fmaxf(t, 0.f) + __logf(1.f + __expf(-fabsf(t)));
 }
 
 // ---------------------------------------------------------------------------

@@ -37,6 +37,26 @@ struct LayerW {
   void* tr_mfma[3] = {};
 };
 
+// Optional device-time accounting of kernel classes (HIP events around launches).
+enum ProfClass { PC_CONV_WIDE_BF16 = 0, PC_CONV_WIDE_F32 = 1, PC_CONV_OTHER = 2, PC_STENCIL = 3,
+                 PC_UPDATE = 4, PC_WARMSTART = 5, PC_COUNT = 6 };
+struct ProfRec {
+  int cls;
+  hipEvent_t e0, e1;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<ProfRec> pending;
+  double ms[PC_COUNT] = {};
+  long long launches[PC_COUNT] = {};
+  unsigned long long* dev_px = nullptr;  // device counters, one per class
+  int begin(int cls, hipStream_t s, ProfRec* r);
+  int end(ProfRec& r, hipStream_t s);
+  int flush();
+  void release();
+};
+
 struct Geometry {
   int n, c, h, w;      // solver images
   int NI, img_div;     // net images and the net-image -> image divisor
@@ -58,4 +78,5 @@ struct idq_ctx {
   idq::Workspace ws;
   int* host_gate = nullptr;  // pinned, for polling
   int host_gate_cap = 0;
+  idq::Profiler prof;
 };

@@ -8,6 +8,8 @@
 // Every pass is   acc[co](p) = sum_{ci, tap} W[co][ci][tap] * a[ci](p + off(tap))
 // with the operand a produced by the prologue (Pro) and the result consumed by
 // the epilogue (Epi); see kernels.h.
+#include <cstdlib>
+
 #include "kernels.h"
 
 namespace idq {
@@ -22,12 +24,9 @@ __device__ inline TM load_operand(const ConvArgs& a, int ni, int ci, int yy, int
   }
   size_t idx = ((static_cast<size_t>(ni) * a.H + yy) * a.W + xx) * a.CI + ci;
   TM v = ld<TM>(static_cast<const TA*>(a.in0), idx);
-  if (a.pro == P_ACT) {
-    return a.act == IDQ_ACT_SOFTPLUS ? softplus_f(v) : v;
-  }
   if (a.pro == P_JVP) {
     TM hd = ld<TM>(static_cast<const TA*>(a.in1), idx);
-    return (a.act == IDQ_ACT_SOFTPLUS ? sigmoid_f(v) : TM(1)) * hd;
+    return (a.act == IDQ_ACT_SOFTPLUS ? dsp_from_a(v) : TM(1)) * hd;
   }
   return v;
 }
@@ -40,6 +39,7 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
   const int co0 = blockIdx.z * 16;
   if (p >= HW) return;
   if (!gate_open(a.gate, a.gate_mask, ni / a.img_div)) return;
+  if (a.work_px && blockIdx.z == 0) atomicAdd(a.work_px, 1ull);
   const int y = p / a.W, x = p - (p / a.W) * a.W;
   const int nco = min(16, a.CO - co0);
   const TM* w = static_cast<const TM*>(a.wgt);
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
       const TS* e0 = static_cast<const TS*>(a.e0);
       TM r;
       switch (a.epi) {
-        case E_STORE: r = acc[j] + b; break;
+        case E_ACT: r = sp ? softplus_f(acc[j] + b) : acc[j] + b; break;
         case E_RES: r = ld<TM>(e0, o) - (acc[j] + b); break;
         case E_SUB: r = ld<TM>(e0, o) - acc[j]; break;
         default: r = acc[j]; break;
@@ -82,18 +82,18 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
       TA* out = static_cast<TA*>(a.out0);
       const TA* e0 = static_cast<const TA*>(a.e0);
       switch (a.epi) {
-        case E_STORE: st(out, o, acc[j] + b); break;
+        case E_ACT: st(out, o, sp ? softplus_f(acc[j] + b) : acc[j] + b); break;
         case E_RAW: st(out, o, acc[j]); break;
         case E_DELTA: {
-          TM h = ld<TM>(e0, o);
-          st(out, o, (sp ? sigmoid_f(h) : TM(1)) * acc[j]);
+          TM av = ld<TM>(e0, o);
+          st(out, o, (sp ? dsp_from_a(av) : TM(1)) * acc[j]);
           break;
         }
         case E_DDOT: {
-          TM h = ld<TM>(e0, o);
+          TM av = ld<TM>(e0, o);
           TM hd = ld<TM>(static_cast<const TA*>(a.e1), o);
           TM t = ld<TM>(static_cast<const TA*>(a.e2), o);
-          TM s1 = sp ? sigmoid_f(h) : TM(1);
+          TM s1 = sp ? dsp_from_a(av) : TM(1);
           TM s2 = sp ? s1 * (TM(1) - s1) : TM(0);
           st(out, o, s2 * hd * t + s1 * acc[j]);
           st(static_cast<TA*>(a.out1), o, s1 * t);
@@ -111,9 +111,33 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
 
 int launch_conv_mfma(const ConvArgs& a, int prec, hipStream_t s);  // k_conv_mfma.hip
 
+// The MFMA kernels read thin (CI <= 4) operands as NCHW state tensors and wide
+// ones as NHWC activations, and write NHWC outputs through E_ACT / E_DELTA /
+// E_RAW / E_DDOT (float32) or NCHW outputs through E_RES / E_SUB / E_RAW.
+static bool mfma_form_ok(const ConvArgs& a, int prec) {
+  const bool in_ok = a.CI <= 4 ? (a.in_fmt == F_NCHW && a.pro == P_NONE) : a.in_fmt == F_NHWC;
+  bool out_ok;
+  if (a.out_fmt == F_NHWC)
+    out_ok = a.epi == E_ACT || a.epi == E_DELTA || a.epi == E_RAW ||
+             (a.epi == E_DDOT && prec == PREC_F32);
+  else
+    out_ok = a.epi == E_RES || a.epi == E_SUB || a.epi == E_RAW;
+  return in_ok && out_ok;
+}
+
+static int force_direct() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("IDQ_FORCE_DIRECT");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v;
+}
+
 int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
   if (a.NI <= 0 || a.H <= 0 || a.W <= 0) return IDQ_OK;
-  if (prec != PREC_F64 && a.wmfma && mfma_supported(prec, a.CI, a.CO))
+  if (prec != PREC_F64 && a.wmfma && !force_direct() && mfma_supported(prec, a.CI, a.CO) &&
+      mfma_form_ok(a, prec))
     return launch_conv_mfma(a, prec, s);
   dim3 grid((a.H * a.W + 255) / 256, a.NI, (a.CO + 15) / 16);
   if (grid.y > 65535) return fail(IDQ_E_INVAL, "too many images in one conv pass");

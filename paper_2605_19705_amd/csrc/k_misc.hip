@@ -357,11 +357,9 @@ __global__ __launch_bounds__(kBlock) void wgrad_kernel(WgradArgs a) {
       if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) continue;
       const TM g = wg_load<TM, TS, TA>(a.g, a.g_fmt, ni, co, a.CO, y, x, a.H, a.W);
       TM av = wg_load<TM, TS, TA>(a.a0, a.a_fmt, ni, ci, a.CI, yy, xx, a.H, a.W);
-      if (a.a_pro == P_ACT) {
-        av = a.act == IDQ_ACT_SOFTPLUS ? softplus_f(av) : av;
-      } else if (a.a_pro == P_JVP) {
+      if (a.a_pro == P_JVP) {
         const TM hd = wg_load<TM, TS, TA>(a.a1, a.a_fmt, ni, ci, a.CI, yy, xx, a.H, a.W);
-        av = (a.act == IDQ_ACT_SOFTPLUS ? sigmoid_f(av) : TM(1)) * hd;
+        av = (a.act == IDQ_ACT_SOFTPLUS ? dsp_from_a(av) : TM(1)) * hd;
       }
       acc += static_cast<double>(g * av);
     }

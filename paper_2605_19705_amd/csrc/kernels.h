@@ -12,21 +12,24 @@ namespace idq {
 //              float accumulation
 enum Prec { PREC_F64 = IDQ_F64, PREC_F32 = IDQ_F32, PREC_BF16 = IDQ_BF16 };
 
+// Activation buffers of the network hold a_l = sigma(h_l) (not h_l): the
+// SoftPlus is evaluated once, in the producing pass's epilogue, and the
+// derivatives the backward passes need are recovered from a:
+//   sigma'(h)  = 1 - exp(-softplus(h)) = -expm1(-a),   sigma''(h) = s (1 - s).
 // Input transform applied while loading a conv operand.
 enum Pro {
-  P_NONE = 0,  // a = in0
-  P_ACT = 1,   // a = sigma(in0)                  (in0 = pre-activation h)
-  P_JVP = 2,   // a = sigma'(in0) * in1           (in0 = h, in1 = tangent h')
+  P_NONE = 0,  // operand = in0
+  P_JVP = 1,   // operand = sigma'(h) * in1, sigma' from in0 = a    (tangent a')
 };
 
 // Output transform of a conv pass (acc = sum over taps and input channels).
 enum Epi {
-  E_STORE = 0,  // out0 = acc + b
+  E_ACT = 0,    // out0 = sigma(acc + b)                   (a_l)
   E_RES = 1,    // out0 = e0 - (acc + b)                   (r = x - N(x))
-  E_DELTA = 2,  // out0 = sigma'(e0) * acc                 (backprop through sigma)
+  E_DELTA = 2,  // out0 = sigma'(h) * acc, from e0 = a     (backprop through sigma)
   E_SUB = 3,    // out0 = e0 - acc                         (grad g = r - J^T r)
   E_RAW = 4,    // out0 = acc
-  E_DDOT = 5,   // out0 = sigma''(e0) e1 e2 + sigma'(e0) acc, out1 = sigma'(e0) e2
+  E_DDOT = 5,   // out0 = sigma''(h) e1 e2 + sigma'(h) acc, out1 = sigma'(h) e2  (e0 = a)
 };
 
 enum Fmt { F_NCHW = 0, F_NHWC = 1 };
@@ -51,6 +54,7 @@ struct ConvArgs {
   const int* gate;      // per solver image phase gate (nullable => always run)
   int gate_mask;        // run image i iff (1 << gate[i]) & gate_mask
   int img_div;          // solver image = net image / img_div
+  unsigned long long* work_px;  // nullable: += output pixels actually computed
 };
 
 // Phase gate values written by the finalize kernel.
@@ -158,7 +162,7 @@ int launch_axpbypcz(double alpha, const void* a, double beta, const void* b, dou
 struct WgradArgs {
   int NI, H, W, CI, CO;
   int g_fmt, a_fmt;
-  int a_pro, act;          // P_NONE | P_ACT | P_JVP on the A operand
+  int a_pro, act;          // P_NONE | P_JVP on the A operand
   const void* g;           // gradient operand (c_out channels)
   const void* a0;          // A operand (c_in channels)
   const void* a1;          // tangent for P_JVP

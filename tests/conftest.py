@@ -17,3 +17,8 @@ def rng():
     """A fresh generator per test, so results do not depend on test order."""
     import numpy as np
     return np.random.default_rng(2024)
+
+
+import faulthandler  # noqa: E402
+
+faulthandler.enable()
