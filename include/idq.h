@@ -117,6 +117,10 @@ typedef struct {
     idq_ws* ws;             /* warm-start network for IDQ_INIT_WARMSTART          */
     int    ws_prec;         /* IDQ_F32 | IDQ_BF16 for the warm-start inference    */
     int    use_graph;       /* 1: replay captured HIP graphs of the iteration     */
+    double* rel_history;    /* host, nullable: n * history_len doubles; entry
+                               [k * n + i] = relative residual of image i after
+                               update k+1 (NaN once the image has stopped)        */
+    int    history_len;     /* rows of rel_history (updates recorded)             */
 } idq_solve_opts;
 
 /* Per-image results of idq_solve (host array of n entries). */

@@ -51,7 +51,8 @@ class SolveOpts(C.Structure):
                 ("switch_tol", C.c_double), ("switch_patience", C.c_int),
                 ("power_iters", C.c_int), ("power_v0", C.c_void_p), ("poll_every", C.c_int),
                 ("init", C.c_int), ("ws", C.c_void_p), ("ws_prec", C.c_int),
-                ("use_graph", C.c_int)]
+                ("use_graph", C.c_int), ("rel_history", C.POINTER(C.c_double)),
+                ("history_len", C.c_int)]
 
 
 class SolveInfo(C.Structure):

@@ -184,7 +184,8 @@ class IDQ:
     def solve(self, y, x0=None, out=None, beta=0.5, tau=0.0, lam=1.0, tol=1e-4, max_iter=1000,
               fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
               switch_tol=1e-3, switch_patience=10, power_iters=30, power_v0=None,
-              poll_every=8, init="y", ws=None, ws_prec="bf16", use_graph=False):
+              poll_every=8, init="y", ws=None, ws_prec="bf16", use_graph=False,
+              history=0):
         o = L.SolveOpts()
         L.lib().idq_solve_opts_default(C.byref(o))
         o.beta, o.tau, o.lambda_, o.tol = float(beta), float(tau), float(lam), float(tol)
@@ -202,6 +203,11 @@ class IDQ:
         o.ws_prec = _PREC[ws_prec]
         o.use_graph = int(bool(use_graph))
         n = y.shape[0]
+        hist = None
+        if history:
+            hist = np.full((int(history), n), np.nan)
+            o.rel_history = hist.ctypes.data_as(C.POINTER(C.c_double))
+            o.history_len = int(history)
         info = (L.SolveInfo * n)()
         x = out if out is not None else torch.empty_like(y)
         code = L.lib().idq_solve(self._h, _ptr(y), _ptr(x0), _ptr(x), *_shape4(y), _dtype_code(y),
@@ -213,6 +219,7 @@ class IDQ:
                           status=np.array([i.status for i in info]),
                           rel=np.array([i.rel for i in info]),
                           tau=float(info[0].tau), code=code)
+        res.history = hist
         return x, res
 
     def backward(self, xbar, y, dl_dx, tau, lam, mode="implicit", adjoint_max_iter=500,

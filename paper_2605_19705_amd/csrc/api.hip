@@ -563,6 +563,14 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   IDQ_TRY(ctx->ws.get(W_STATE, sizeof(ImgState) * n, &state));
   IDQ_TRY(ctx->ws.get(W_GATE, sizeof(int) * n, &gate));
   IDQ_TRY(ctx->ws.get(W_BETA, sizeof(double) * n, &beta));
+  void* hist = nullptr;
+  const int hist_len = (o->rel_history && o->history_len > 0) ? o->history_len : 0;
+  if (hist_len) {
+    IDQ_TRY(ctx->ws.get(W_HIST, sizeof(double) * n * hist_len, &hist));
+    std::vector<double> nan(static_cast<size_t>(n) * hist_len, NAN);
+    IDQ_HIP(hipMemcpyAsync(hist, nan.data(), sizeof(double) * nan.size(), hipMemcpyHostToDevice, s));
+    IDQ_HIP(hipStreamSynchronize(s));
+  }
   // x^0 and x^{-1} = x^0
   if (x0) {
     IDQ_TRY(copy_state(x0, xb[0], sbytes, s));
@@ -658,6 +666,8 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
       ua.partials = static_cast<double*>(part);
       ua.nblk = nblk;
       fa.buf_index = (t + 1) % 2;
+      fa.history = (hist && t < hist_len) ? static_cast<double*>(hist) : nullptr;
+      fa.step = t;
       IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
         IDQ_TRY(launch_update(ua, dtype, s));
         return launch_finalize(fa, s);
@@ -677,6 +687,9 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   IDQ_TRY(launch_gather_result(xb[0], xb[1], x_out, static_cast<const ImgState*>(state), n, g.per,
                                dtype, s));
   IDQ_HIP(hipMemcpyAsync(hs.data(), state, sizeof(ImgState) * n, hipMemcpyDeviceToHost, s));
+  if (hist_len)
+    IDQ_HIP(hipMemcpyAsync(o->rel_history, hist, sizeof(double) * n * hist_len,
+                           hipMemcpyDeviceToHost, s));
   IDQ_HIP(hipStreamSynchronize(s));
   int rc = IDQ_OK;
   for (int i = 0; i < n; ++i) {

@@ -68,10 +68,13 @@ __device__ inline double sigmoid_f(double t) {
 // sigma(h) = 1 - exp(-softplus(h)) = -expm1(-a).
 __device__ inline float dsp_from_a(float a) { return -expm1f(-a); }
 __device__ inline double dsp_from_a(double a) { return -expm1(-a); }
-// Fast variant for bfloat16 passes (operands carry 8 significant bits).
-__device__ inline float dsp_from_a_fast(float a) { return 1.f - __expf(-a); }
+// Fast variants for bfloat16 passes (operands carry 8 significant bits): the
+// bare hardware exp2 / log2 (v_exp_f32, v_log_f32) without range reduction.
+__device__ inline float exp_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ inline float log_fast(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+__device__ inline float dsp_from_a_fast(float a) { return 1.f - exp_fast(-a); }
 __device__ inline float softplus_fast(float t) {
-  return fmaxf(t, 0.f) + __logf(1.f + __expf(-fabsf(t)));
+  return fmaxf(t, 0.f) + log_fast(1.f + exp_fast(-fabsf(t)));
 }
 
 // ---------------------------------------------------------------------------

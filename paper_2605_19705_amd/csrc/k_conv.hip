@@ -112,17 +112,21 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
 int launch_conv_mfma(const ConvArgs& a, int prec, hipStream_t s);  // k_conv_mfma.hip
 
 // The MFMA kernels read thin (CI <= 4) operands as NCHW state tensors and wide
-// ones as NHWC activations, and write NHWC outputs through E_ACT / E_DELTA /
-// E_RAW / E_DDOT (float32) or NCHW outputs through E_RES / E_SUB / E_RAW.
+// ones as NHWC activations, and write NHWC outputs (CO > 4) through E_ACT /
+// E_DELTA / E_RAW / E_DDOT (float32) or NCHW outputs (CO <= 4) through E_RES /
+// E_SUB; the float32 tangent prologue feeds E_RAW (wide) or E_SUB (thin).
 static bool mfma_form_ok(const ConvArgs& a, int prec) {
-  const bool in_ok = a.CI <= 4 ? (a.in_fmt == F_NCHW && a.pro == P_NONE) : a.in_fmt == F_NHWC;
+  const bool in_ok = a.CI <= 4 ? (a.in_fmt == F_NCHW && a.pro == P_NONE)
+                               : (a.in_fmt == F_NHWC && (a.pro == P_NONE || prec == PREC_F32));
   bool out_ok;
-  if (a.out_fmt == F_NHWC)
-    out_ok = a.epi == E_ACT || a.epi == E_DELTA || a.epi == E_RAW ||
-             (a.epi == E_DDOT && prec == PREC_F32);
+  if (a.CO > 4)
+    out_ok = a.out_fmt == F_NHWC && (a.epi == E_ACT || a.epi == E_DELTA || a.epi == E_RAW ||
+                                     (a.epi == E_DDOT && prec == PREC_F32));
   else
-    out_ok = a.epi == E_RES || a.epi == E_SUB || a.epi == E_RAW;
-  return in_ok && out_ok;
+    out_ok = a.out_fmt == F_NCHW && (a.epi == E_RES || a.epi == E_SUB) &&
+             (a.pro == P_NONE || a.epi == E_SUB);
+  const bool jvp_ok = a.pro != P_JVP || (a.CO > 4 ? a.epi == E_RAW : a.epi == E_SUB);
+  return in_ok && out_ok && jvp_ok;
 }
 
 static int force_direct() {

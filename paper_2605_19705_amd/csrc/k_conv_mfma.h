@@ -1,0 +1,510 @@
+// Implicit-GEMM 3x3 convolution on the gfx950 matrix cores (kernel template;
+// instantiated per arithmetic in k_conv_mfma_bf16.hip / k_conv_mfma_f32.hip).
+//
+// One pass computes, for every output pixel p and output channel co,
+//     acc[co](p) = sum_k Wm[co][k] * X[k](p),   k = tap * CI + ci,
+//     X[tap * CI + ci](p) = a[ci](p + (tap / 3 - 1, tap % 3 - 1))   (zero outside)
+// as D = Wm (M = co) x X (N = pixels), K = 9 * CI, on 16x16 MFMA tiles:
+//   bf16: v_mfma_f32_16x16x32_bf16  (K chunk 32: lane group g owns k 8g..8g+7)
+//   fp32: v_mfma_f32_16x16x4_f32    (K chunk 16: lane group g owns k 4g..4g+3 as
+//         a float4 whose component s feeds the s-th of four MFMAs; the same
+//         k permutation is applied to the weights, so the sum is unchanged)
+// Operand / accumulator lane layouts (16x16 tiles): lane l supplies row l%16 of
+// A and column l%16 of B for its k slice; it receives D rows 4*(l/16)+i,
+// column l%16, i = 0..3.
+//
+// Work decomposition: a persistent grid of 256-thread workgroups walks the
+// 16x16-pixel output tiles of all images.  Each tile's (18 x 18)-pixel halo
+// tile sits in LDS (pixel-major, channels contiguous, a 16-byte pad per pixel
+// keeps the B-fragment reads conflict-free); wave w computes output rows
+// 4w..4w+3 for every output channel.  While a tile is computed, the next
+// tile's halo is already being fetched from HBM into registers, so global
+// latency overlaps the matrix-core work.  When a K chunk never straddles two
+// taps (CI a multiple of the chunk), the B fragments of one input row are
+// loaded once and reused by the three kernel rows (dy) that read it.
+// BF16 weights live in LDS for the whole kernel (staged once per workgroup,
+// already in fragment order); FP32 weights are read in fragment order from
+// global memory (their matrix-core rate is 1/16 of bf16, so L2 traffic is
+// small).  Thin layers (CI <= 4, the image-facing convs) gather their operand
+// from a per-pixel 4-channel LDS tile.
+#pragma once
+
+#include "kernels.h"
+
+namespace idq {
+namespace mfma {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4_t;
+
+constexpr int kThreads = 256;
+constexpr int TH = 16, TW = 16;
+constexpr int HW_ = TW + 2, HH_ = TH + 2, NPIX = HW_ * HH_;
+constexpr int RW = 4;  // output rows per wave
+
+template <int PREC, int CI, int CO>
+struct Cfg {
+  static constexpr bool BF = PREC == PREC_BF16;
+  static constexpr int ES = BF ? 2 : 4;        // LDS element bytes
+  static constexpr int V = BF ? 8 : 4;         // k elements per lane per chunk (16 bytes)
+  static constexpr int KC = 4 * V;             // k per chunk
+  static constexpr int K = 9 * CI;
+  static constexpr int NCH = (K + KC - 1) / KC;
+  static constexpr int NJ = (CO + 15) / 16;
+  static constexpr bool VEC = (CI % V) == 0;
+  static constexpr bool ROWS = (CI % KC) == 0;  // chunks align with taps: reuse rows
+  static constexpr int CPT = ROWS ? CI / KC : 0;  // chunks per tap
+  static constexpr int CIP = VEC ? CI : 4;
+  static constexpr int PIXB = CIP * ES + (VEC ? 16 : 0);
+  static constexpr int LDS_IN = (NPIX * PIXB + 15) / 16 * 16;
+  static constexpr bool WLDS = BF;
+  static constexpr int WBYTES = NCH * NJ * 64 * 16;
+  static constexpr int LDS = LDS_IN + (WLDS ? WBYTES : 0);
+  // prefetch: 16-byte items (VEC) or floats (gather) per thread for one tile
+  static constexpr int VPP = VEC ? CI / V : 0;
+  static constexpr int ITEMS = VEC ? (NPIX * VPP + kThreads - 1) / kThreads
+                                   : (NPIX * CI + kThreads - 1) / kThreads;
+  // fp32 reads its weights from global memory: a short unroll keeps the
+  // hoisted loads within the register file
+  static constexpr int UNROLL = BF ? NCH : 2;
+};
+
+__device__ inline unsigned pack2(bf16 lo, bf16 hi) {
+  return static_cast<unsigned>(lo.u) | (static_cast<unsigned>(hi.u) << 16);
+}
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
+// two floats -> packed bf16 pair (round to nearest even, v_cvt_pk_bf16_f32)
+__device__ inline unsigned pk_bf16(float lo, float hi) {
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
+}
+__device__ inline float u2f(unsigned u) { return __builtin_bit_cast(float, u); }
+__device__ inline unsigned f2u(float f) { return __builtin_bit_cast(unsigned, f); }
+
+template <bool BF>
+__device__ inline float lds_scalar(const char* p) {
+  if (BF) {
+    bf16 v;
+    v.u = *reinterpret_cast<const uint16_t*>(p);
+    return bf2f(v);
+  }
+  return *reinterpret_cast<const float*>(p);
+}
+
+// Registers holding one tile's halo between its global load and its LDS store.
+template <class C, int PRO>
+struct Prefetch {
+  u32x4_t v[C::VEC ? C::ITEMS : 1];
+  u32x4_t w[(C::VEC && PRO == P_JVP) ? C::ITEMS : 1];
+  float s[C::VEC ? 1 : C::ITEMS];
+};
+
+// Epilogue operand of one tile (E_DELTA): 4 channels per (row, channel block).
+template <class C>
+struct EpiPrefetch {
+  u32x4_t v[RW][C::NJ];
+};
+
+template <class C, int CI, int PRO>
+__device__ inline void load_tile(const ConvArgs& a, Prefetch<C, PRO>& pf, int ni, int ty0,
+                                 int tx0, int tid) {
+#pragma unroll
+  for (int k = 0; k < C::ITEMS; ++k) {
+    const int it = tid + k * kThreads;
+    if (C::VEC) {
+      u32x4_t val = {0u, 0u, 0u, 0u}, hd = {0u, 0u, 0u, 0u};
+      if (it < NPIX * C::VPP) {
+        const int p = it / C::VPP, v = it - (it / C::VPP) * C::VPP;
+        const int ly = p / HW_, lx = p - (p / HW_) * HW_;
+        const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+          const size_t e = (((static_cast<size_t>(ni) * a.H + gy) * a.W + gx) * CI + v * C::V) * C::ES;
+          val = *reinterpret_cast<const u32x4_t*>(static_cast<const char*>(a.in0) + e);
+          if (PRO == P_JVP) hd = *reinterpret_cast<const u32x4_t*>(static_cast<const char*>(a.in1) + e);
+        }
+      }
+      pf.v[k] = val;
+      if (PRO == P_JVP) pf.w[k] = hd;
+    } else {
+      float val = 0.f;
+      if (it < NPIX * CI) {
+        const int p = it / CI, ci = it - (it / CI) * CI;
+        const int ly = p / HW_, lx = p - (p / HW_) * HW_;
+        const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+          val = static_cast<const float*>(a.in0)[((static_cast<size_t>(ni) * CI + ci) * a.H + gy) * a.W + gx];
+      }
+      pf.s[k] = val;
+    }
+  }
+}
+
+template <class C, int CI, int PRO>
+__device__ inline void store_tile(const ConvArgs& a, const Prefetch<C, PRO>& pf, char* lin,
+                                  int tid) {
+  const bool sp = a.act == IDQ_ACT_SOFTPLUS;
+#pragma unroll
+  for (int k = 0; k < C::ITEMS; ++k) {
+    const int it = tid + k * kThreads;
+    if (C::VEC) {
+      if (it < NPIX * C::VPP) {
+        const int p = it / C::VPP, v = it - (it / C::VPP) * C::VPP;
+        u32x4_t val = pf.v[k];
+        if (PRO == P_JVP) {
+          const u32x4_t hd = pf.w[k];
+          if (C::BF) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              bf16 lo, hi, dlo, dhi;
+              lo.u = val[q] & 0xffffu;
+              hi.u = val[q] >> 16;
+              dlo.u = hd[q] & 0xffffu;
+              dhi.u = hd[q] >> 16;
+              const float s0 = sp ? dsp_from_a_fast(bf2f(lo)) : 1.f;
+              const float s1 = sp ? dsp_from_a_fast(bf2f(hi)) : 1.f;
+              val[q] = pack2(f2bf(s0 * bf2f(dlo)), f2bf(s1 * bf2f(dhi)));
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              val[q] = f2u((sp ? dsp_from_a(u2f(val[q])) : 1.f) * u2f(hd[q]));
+          }
+        }
+        *reinterpret_cast<u32x4_t*>(lin + p * C::PIXB + v * 16) = val;
+      }
+    } else {
+      if (it < NPIX * CI) {
+        const int p = it / CI, ci = it - (it / CI) * CI;
+        char* d = lin + p * C::PIXB + ci * C::ES;
+        if (C::BF)
+          *reinterpret_cast<uint16_t*>(d) = f2bf(pf.s[k]).u;
+        else
+          *reinterpret_cast<float*>(d) = pf.s[k];
+      }
+    }
+  }
+}
+
+template <class C>
+__device__ inline void mma(f32x4_t& acc, const u32x4_t& af, const u32x4_t& bf) {
+  if (C::BF) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, af),
+                                                  __builtin_bit_cast(bf16x8_t, bf), acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(u2f(af[s]), u2f(bf[s]), acc, 0, 0, 0);
+  }
+}
+
+template <int PREC, int CI, int CO, int PRO, int EPI>
+__global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int ntx, int nty,
+                                                               int ntiles) {
+  using C = Cfg<PREC, CI, CO>;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  char* lin = smem;
+  const u32x4_t* lw = reinterpret_cast<const u32x4_t*>(smem + C::LDS_IN);
+  const u32x4_t* gw = static_cast<const u32x4_t*>(a.wmfma);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, c16 = lane & 15;
+  const bool sp = a.act == IDQ_ACT_SOFTPLUS;
+  const int tiles_per_img = ntx * nty;
+  auto open = [&](int t) { return gate_open(a.gate, a.gate_mask, (t / tiles_per_img) / a.img_div); };
+
+  if (C::WLDS) {
+    u32x4_t* dst = reinterpret_cast<u32x4_t*>(smem + C::LDS_IN);
+    for (int i = tid; i < C::NCH * C::NJ * 64; i += kThreads) dst[i] = gw[i];
+  }
+
+  // bias of the 16 output channels this lane owns in the epilogue
+  float bias_r[C::NJ][4];
+  {
+    const float* bias = static_cast<const float*>(a.bias);
+#pragma unroll
+    for (int j = 0; j < C::NJ; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = 16 * j + 4 * g + i;
+        bias_r[j][i] = (bias && co < CO) ? bias[co] : 0.f;
+      }
+  }
+
+  int t = blockIdx.x;
+  while (t < ntiles && !open(t)) t += gridDim.x;
+  Prefetch<C, PRO> pf;
+  if (t < ntiles) {
+    const int ni = t / tiles_per_img, rem = t - ni * tiles_per_img;
+    load_tile<C, CI, PRO>(a, pf, ni, (rem / ntx) * TH, (rem % ntx) * TW, tid);
+  }
+  while (t < ntiles) {
+    const int ni = t / tiles_per_img;
+    const int rem = t - ni * tiles_per_img;
+    const int ty0 = (rem / ntx) * TH, tx0 = (rem % ntx) * TW;
+    __syncthreads();  // the previous tile's fragments have been read
+    store_tile<C, CI, PRO>(a, pf, lin, tid);
+    __syncthreads();
+    int tn = t + gridDim.x;
+    while (tn < ntiles && !open(tn)) tn += gridDim.x;
+    if (tn < ntiles) {
+      const int nn = tn / tiles_per_img, rn = tn - nn * tiles_per_img;
+      load_tile<C, CI, PRO>(a, pf, nn, (rn / ntx) * TH, (rn % ntx) * TW, tid);
+    }
+    if (a.work_px && tid == 0) {
+      const int vh = a.H - ty0 < TH ? a.H - ty0 : TH, vw = a.W - tx0 < TW ? a.W - tx0 : TW;
+      atomicAdd(a.work_px, static_cast<unsigned long long>(vh * vw));
+    }
+    // the epilogue's sigma(h) operand of this tile, fetched now so that its
+    // latency hides behind the matrix-core work
+    EpiPrefetch<C> ep;
+    constexpr bool pre_e0 = EPI == E_DELTA && CO % 4 == 0;
+    if (pre_e0) {
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int oy = ty0 + wv * RW + r, ox = tx0 + c16;
+#pragma unroll
+        for (int j = 0; j < C::NJ; ++j) {
+          const int co0 = 16 * j + 4 * g;
+          ep.v[r][j] = u32x4_t{0u, 0u, 0u, 0u};
+          if (oy < a.H && ox < a.W && co0 < CO) {
+            const size_t o = ((static_cast<size_t>(ni) * a.H + oy) * a.W + ox) * CO + co0;
+            if (C::BF) {
+              const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const bf16*>(a.e0) + o);
+              ep.v[r][j] = u32x4_t{u.x, u.y, 0u, 0u};
+            } else {
+              ep.v[r][j] = *reinterpret_cast<const u32x4_t*>(static_cast<const float*>(a.e0) + o);
+            }
+          }
+        }
+      }
+    }
+    // ---- K loop on the matrix cores ------------------------------------------
+    f32x4_t acc[RW][C::NJ];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int j = 0; j < C::NJ; ++j) acc[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    if (C::ROWS) {
+      // k = (dy*3 + dx) * CI + c*KC + slice: load the RW+2 input rows once per
+      // (dx, c) and reuse them for dy = 0, 1, 2
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+#pragma unroll (C::BF ? C::CPT : 1)
+        for (int c = 0; c < C::CPT; ++c) {
+          u32x4_t brow[RW + 2];
+          const int coff = (c * C::KC + g * C::V) * C::ES;
+#pragma unroll
+          for (int ir = 0; ir < RW + 2; ++ir) {
+            const int pix = (wv * RW + ir) * HW_ + c16 + dx;
+            brow[ir] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + coff);
+          }
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            const int ch = (dy * 3 + dx) * C::CPT + c;
+            u32x4_t af[C::NJ];
+#pragma unroll
+            for (int j = 0; j < C::NJ; ++j) af[j] = C::WLDS ? lw[(ch * C::NJ + j) * 64 + lane]
+                                                         : gw[(ch * C::NJ + j) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], af[j], brow[r + dy]);
+          }
+        }
+      }
+    } else {
+#pragma unroll C::UNROLL
+      for (int ch = 0; ch < C::NCH; ++ch) {
+        const int kb = ch * C::KC + g * C::V;
+        u32x4_t af[C::NJ];
+#pragma unroll
+        for (int j = 0; j < C::NJ; ++j) af[j] = C::WLDS ? lw[(ch * C::NJ + j) * 64 + lane]
+                                                     : gw[(ch * C::NJ + j) * 64 + lane];
+        u32x4_t bfr[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          const int row = wv * RW + r;
+          if (C::VEC) {
+            if (kb < C::K) {
+              const int tap = kb / CI, ci0 = kb - (kb / CI) * CI;
+              const int pix = (row + tap / 3) * HW_ + c16 + tap % 3;
+              bfr[r] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + ci0 * C::ES);
+            } else {
+              bfr[r] = u32x4_t{0u, 0u, 0u, 0u};
+            }
+          } else {
+            float vals[C::V];
+#pragma unroll
+            for (int e = 0; e < C::V; ++e) {
+              const int k = kb + e;
+              float v = 0.f;
+              if (k < C::K) {
+                const int tap = k / CI, ci = k - (k / CI) * CI;
+                const int pix = (row + tap / 3) * HW_ + c16 + tap % 3;
+                v = lds_scalar<C::BF>(lin + pix * C::PIXB + ci * C::ES);
+              }
+              vals[e] = v;
+            }
+            if (C::BF) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) bfr[r][q] = pk_bf16(vals[2 * q], vals[2 * q + 1]);
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) bfr[r][q] = f2u(vals[q]);
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+          for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], af[j], bfr[r]);
+      }
+    }
+    // ---- epilogue ----------------------------------------------------------------
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int oy = ty0 + wv * RW + r, ox = tx0 + c16;
+      if (oy >= a.H || ox >= a.W) continue;
+#pragma unroll
+      for (int j = 0; j < C::NJ; ++j) {
+        const int co0 = 16 * j + 4 * g;
+        if (co0 >= CO) continue;
+        if constexpr (EPI != E_RES && EPI != E_SUB) {
+          const size_t o = ((static_cast<size_t>(ni) * a.H + oy) * a.W + ox) * CO + co0;
+          float v[4], w1[4];
+          f32x4_t dd0 = {0.f, 0.f, 0.f, 0.f}, dd1 = dd0, dd2 = dd0;
+          bool two = false;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int co = co0 + i;
+            const float x = acc[r][j][i];
+            float res = x;
+            w1[i] = 0.f;
+            if (co < CO) {
+              if constexpr (EPI == E_ACT) {
+                  const float hv = x + bias_r[j][i];
+                  res = sp ? (C::BF ? softplus_fast(hv) : softplus_f(hv)) : hv;
+              } else if constexpr (EPI == E_DELTA) {
+                  float av;
+                  if (pre_e0) {
+                    if (C::BF) {
+                      bf16 hb;
+                      hb.u = static_cast<uint16_t>(ep.v[r][j][i >> 1] >> ((i & 1) * 16));
+                      av = bf2f(hb);
+                    } else {
+                      av = u2f(ep.v[r][j][i]);
+                    }
+                  } else {
+                    av = C::BF ? bf2f(static_cast<const bf16*>(a.e0)[o + i])
+                               : static_cast<const float*>(a.e0)[o + i];
+                  }
+                  res = (sp ? (C::BF ? dsp_from_a_fast(av) : dsp_from_a(av)) : 1.f) * x;
+              } else if constexpr (EPI == E_DDOT) {
+                  // float32 passes only (the HVP is not run in bf16)
+                  if (CO % 4 == 0 && i == 0) {
+                    dd0 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e0) + o);
+                    dd1 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e1) + o);
+                    dd2 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e2) + o);
+                  }
+                  const float av = CO % 4 == 0 ? dd0[i] : static_cast<const float*>(a.e0)[o + i];
+                  const float hd = CO % 4 == 0 ? dd1[i] : static_cast<const float*>(a.e1)[o + i];
+                  const float tv = CO % 4 == 0 ? dd2[i] : static_cast<const float*>(a.e2)[o + i];
+                  const float s1 = sp ? dsp_from_a(av) : 1.f;
+                  const float s2 = sp ? s1 * (1.f - s1) : 0.f;
+                  res = s2 * hd * tv + s1 * x;
+                  w1[i] = s1 * tv;
+                  two = true;
+              }
+            }
+            v[i] = res;
+          }
+          if (C::BF) {
+            bf16* out = static_cast<bf16*>(a.out0) + o;
+            if (CO % 4 == 0) {
+              uint2 pk;
+              pk.x = pk_bf16(v[0], v[1]);
+              pk.y = pk_bf16(v[2], v[3]);
+              *reinterpret_cast<uint2*>(out) = pk;
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (co0 + i < CO) out[i] = f2bf(v[i]);
+            }
+          } else {
+            float* out = static_cast<float*>(a.out0) + o;
+            if (CO % 4 == 0) {
+              *reinterpret_cast<f32x4_t*>(out) = f32x4_t{v[0], v[1], v[2], v[3]};
+              if (two)
+                *reinterpret_cast<f32x4_t*>(static_cast<float*>(a.out1) + o) =
+                    f32x4_t{w1[0], w1[1], w1[2], w1[3]};
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (co0 + i < CO) {
+                  out[i] = v[i];
+                  if (two) static_cast<float*>(a.out1)[o + i] = w1[i];
+                }
+            }
+          }
+        } else {
+          // state tensor output in NCHW (float)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int co = co0 + i;
+            if (co >= CO) break;
+            const size_t o = ((static_cast<size_t>(ni) * CO + co) * a.H + oy) * a.W + ox;
+            const float x = acc[r][j][i];
+            const float* e0 = static_cast<const float*>(a.e0);
+            float res;
+            if constexpr (EPI == E_RES)
+              res = e0[o] - (x + bias_r[j][i]);
+            else
+              res = e0[o] - x;
+            static_cast<float*>(a.out0)[o] = res;
+          }
+        }
+      }
+    }
+    t = tn;
+  }
+}
+
+template <int PREC, int CI, int CO, int PRO, int EPI>
+int launch_shape(const ConvArgs& a, hipStream_t s) {
+  using C = Cfg<PREC, CI, CO>;
+  static_assert(C::LDS <= 160 * 1024, "LDS budget");
+  static_assert(CO > 4 || EPI == E_RES || EPI == E_SUB, "thin outputs are NCHW state tensors");
+  static bool attr_set = false;
+  static int max_blocks = 0;
+  auto kern = conv_mfma_kernel<PREC, CI, CO, PRO, EPI>;
+  if (!attr_set) {
+    IDQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS));
+    int dev = 0, ncu = 0, occ = 0;
+    IDQ_HIP(hipGetDevice(&dev));
+    IDQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    IDQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, C::LDS));
+    if (occ < 1) return fail(IDQ_E_UNSUPPORTED, "MFMA conv does not fit on a compute unit");
+    max_blocks = ncu * occ;
+    attr_set = true;
+  }
+  const int ntx = (a.W + TW - 1) / TW, nty = (a.H + TH - 1) / TH;
+  const long long nt = static_cast<long long>(a.NI) * ntx * nty;
+  if (nt > 0x7fffffff) return fail(IDQ_E_INVAL, "too many tiles");
+  const int ntiles = static_cast<int>(nt);
+  const int grid = ntiles < max_blocks ? ntiles : max_blocks;
+  kern<<<grid, kThreads, C::LDS, s>>>(a, ntx, nty, ntiles);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+// (CI, CO) pairs with an MFMA instantiation: the 3->64->...->64->3 and
+// 1->16->16->1 regularizers, the warm-start encoder-decoder, and their
+// transposes.  Image-facing outputs (CO <= 4) are NCHW state tensors.
+#define IDQ_MFMA_WIDE(X) \
+  X(1, 16) X(16, 16) X(3, 64) X(64, 64) X(3, 32) X(32, 32) X(32, 64) X(64, 32) X(96, 32) X(32, 96)
+#define IDQ_MFMA_THIN(X) X(16, 1) X(64, 3) X(32, 3)
+
+}  // namespace mfma
+}  // namespace idq

@@ -247,6 +247,7 @@ __global__ void finalize_kernel(FinalizeArgs a) {
     }
     gate = s.prec;
   }
+  if (a.history) a.history[static_cast<size_t>(a.step) * a.n + i] = rel;
   a.st[i] = s;
   a.gate[i] = s.done ? G_DONE : gate;
   a.beta_eff[i] = s.beta_eff;

@@ -139,6 +139,8 @@ struct FinalizeArgs {
   double beta, tol, restart_B2, switch_tol;
   int max_iter, fixed_iters, switch_patience;
   int buf_index;        // ping-pong buffer holding the new iterate
+  double* history;      // nullable: [step][n] relative residuals
+  int step;             // global update index of this finalize
 };
 int launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // x_out[img] = bufs[st[img].last_buf][img]
