@@ -272,3 +272,80 @@ class IDQSolve(torch.autograd.Function):
         ldt, ldev = fctx.lam_meta
         return (None, dtheta.to(device=tdev, dtype=tdt),
                 torch.tensor(dlam, dtype=ldt, device=ldev), None, None, None)
+
+
+class WarmStart:
+    """Learned initial iterate x0 = y + W_phi(y) (``idq_ws_*`` of the C ABI).
+
+    ``layers``: the 9 (W, b) pairs of the encoder-decoder, float64 arrays.
+    Images are float32 CUDA tensors of shape (n, 3, h, w) with h, w even.
+    """
+
+    def __init__(self, layers, device=0):
+        lib = L.lib()
+        flat = np.ascontiguousarray(pack_layers(layers))
+        n = int(lib.idq_ws_num_params())
+        if flat.size != n:
+            raise ValueError(f"warm-start network takes {n} parameters, got {flat.size}")
+        h = C.c_void_p()
+        L.check(lib.idq_ws_create(C.byref(h), flat.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                  int(device)))
+        self._h = h
+        self.device = device
+        self.num_params = n
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().idq_ws_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(self.num_params, np.float64)
+        L.check(L.lib().idq_ws_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(np.asarray(flat, np.float64))
+        if flat.size != self.num_params:
+            raise ValueError("parameter count mismatch")
+        L.check(L.lib().idq_ws_set_params(self._h, flat.ctypes.data_as(C.POINTER(C.c_double))))
+
+    @staticmethod
+    def _check(y):
+        if y.dtype != torch.float32:
+            raise TypeError("warm-start images are float32")
+        return _shape4(y)
+
+    def forward(self, y, prec="bf16", out=None):
+        n, c, h, w = self._check(y)
+        out = torch.empty_like(y) if out is None else out
+        L.check(L.lib().idq_ws_forward(self._h, _ptr(y), _ptr(out), n, c, h, w, _PREC[prec],
+                                       _stream()))
+        return out
+
+    def grad(self, y, target, prec="f32"):
+        """(loss, flat float32 gradient tensor) of mean((y + W(y) - target)^2)."""
+        n, c, h, w = self._check(y)
+        if target.shape != y.shape or target.dtype != torch.float32:
+            raise ValueError("target must match y")
+        g = torch.empty(self.num_params, dtype=torch.float32, device=y.device)
+        loss = C.c_double()
+        L.check(L.lib().idq_ws_grad(self._h, _ptr(y), _ptr(target), _ptr(g), n, c, h, w,
+                                    _PREC[prec], C.byref(loss), _stream()))
+        return loss.value, g
+
+    def train_step(self, y, target, lr, prec="bf16", want_loss=True):
+        n, c, h, w = self._check(y)
+        if target.shape != y.shape or target.dtype != torch.float32:
+            raise ValueError("target must match y")
+        loss = C.c_double()
+        L.check(L.lib().idq_ws_train_step(self._h, _ptr(y), _ptr(target), n, c, h, w,
+                                          _PREC[prec], float(lr),
+                                          C.byref(loss) if want_loss else None, _stream()))
+        return loss.value if want_loss else None

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
       switch (a.epi) {
         case E_ACT: r = sp ? softplus_f(acc[j] + b) : acc[j] + b; break;
         case E_RES: r = ld<TM>(e0, o) - (acc[j] + b); break;
+        case E_ADD: r = ld<TM>(e0, o) + (acc[j] + b); break;
         case E_SUB: r = ld<TM>(e0, o) - acc[j]; break;
         default: r = acc[j]; break;
       }
@@ -123,7 +124,7 @@ static bool mfma_form_ok(const ConvArgs& a, int prec) {
     out_ok = a.out_fmt == F_NHWC && (a.epi == E_ACT || a.epi == E_DELTA || a.epi == E_RAW ||
                                      (a.epi == E_DDOT && prec == PREC_F32));
   else
-    out_ok = a.out_fmt == F_NCHW && (a.epi == E_RES || a.epi == E_SUB) &&
+    out_ok = a.out_fmt == F_NCHW && (a.epi == E_RES || a.epi == E_SUB || a.epi == E_ADD) &&
              (a.pro == P_NONE || a.epi == E_SUB);
   const bool jvp_ok = a.pro != P_JVP || (a.CO > 4 ? a.epi == E_RAW : a.epi == E_SUB);
   return in_ok && out_ok && jvp_ok;

@@ -287,30 +287,40 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       for (int j = 0; j < C::NJ; ++j) acc[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     if (C::ROWS) {
       // k = (dy*3 + dx) * CI + c*KC + slice: load the RW+2 input rows once per
-      // (dx, c) and reuse them for dy = 0, 1, 2
+      // (dx, c) and reuse them for dy = 0, 1, 2.  The weight fragments of the
+      // next (dx, c, dy) group are fetched while the current group's MFMAs
+      // run (for fp32 they come from L2, whose latency would otherwise stall
+      // every group).
+      auto load_af = [&](u32x4_t* dst, int dxc, int dy) {
+        const int ch = (dy * 3 + dxc / C::CPT) * C::CPT + dxc % C::CPT;
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-#pragma unroll (C::BF ? C::CPT : 1)
-        for (int c = 0; c < C::CPT; ++c) {
-          u32x4_t brow[RW + 2];
-          const int coff = (c * C::KC + g * C::V) * C::ES;
+        for (int j = 0; j < C::NJ; ++j) dst[j] = C::WLDS ? lw[(ch * C::NJ + j) * 64 + lane]
+                                                      : gw[(ch * C::NJ + j) * 64 + lane];
+      };
+      u32x4_t afc[C::NJ], afn[C::NJ];
+      load_af(afc, 0, 0);
+#pragma unroll (C::BF ? 3 * C::CPT : 1)
+      for (int dxc = 0; dxc < 3 * C::CPT; ++dxc) {
+        const int dx = dxc / C::CPT, c = dxc % C::CPT;
+        u32x4_t brow[RW + 2];
+        const int coff = (c * C::KC + g * C::V) * C::ES;
 #pragma unroll
-          for (int ir = 0; ir < RW + 2; ++ir) {
-            const int pix = (wv * RW + ir) * HW_ + c16 + dx;
-            brow[ir] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + coff);
-          }
+        for (int ir = 0; ir < RW + 2; ++ir) {
+          const int pix = (wv * RW + ir) * HW_ + c16 + dx;
+          brow[ir] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + coff);
+        }
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy) {
-            const int ch = (dy * 3 + dx) * C::CPT + c;
-            u32x4_t af[C::NJ];
+        for (int dy = 0; dy < 3; ++dy) {
+          if (dy < 2)
+            load_af(afn, dxc, dy + 1);
+          else if (dxc + 1 < 3 * C::CPT)
+            load_af(afn, dxc + 1, 0);
 #pragma unroll
-            for (int j = 0; j < C::NJ; ++j) af[j] = C::WLDS ? lw[(ch * C::NJ + j) * 64 + lane]
-                                                         : gw[(ch * C::NJ + j) * 64 + lane];
+          for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int r = 0; r < RW; ++r)
+            for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], afc[j], brow[r + dy]);
 #pragma unroll
-              for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], af[j], brow[r + dy]);
-          }
+          for (int j = 0; j < C::NJ; ++j) afc[j] = afn[j];
         }
       }
     } else {
@@ -370,7 +380,7 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       for (int j = 0; j < C::NJ; ++j) {
         const int co0 = 16 * j + 4 * g;
         if (co0 >= CO) continue;
-        if constexpr (EPI != E_RES && EPI != E_SUB) {
+        if constexpr (EPI != E_RES && EPI != E_SUB && EPI != E_ADD) {
           const size_t o = ((static_cast<size_t>(ni) * a.H + oy) * a.W + ox) * CO + co0;
           float v[4], w1[4];
           f32x4_t dd0 = {0.f, 0.f, 0.f, 0.f}, dd1 = dd0, dd2 = dd0;
@@ -459,6 +469,8 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
             float res;
             if constexpr (EPI == E_RES)
               res = e0[o] - (x + bias_r[j][i]);
+            else if constexpr (EPI == E_ADD)
+              res = e0[o] + (x + bias_r[j][i]);
             else
               res = e0[o] - x;
             static_cast<float*>(a.out0)[o] = res;
@@ -474,7 +486,8 @@ template <int PREC, int CI, int CO, int PRO, int EPI>
 int launch_shape(const ConvArgs& a, hipStream_t s) {
   using C = Cfg<PREC, CI, CO>;
   static_assert(C::LDS <= 160 * 1024, "LDS budget");
-  static_assert(CO > 4 || EPI == E_RES || EPI == E_SUB, "thin outputs are NCHW state tensors");
+  static_assert(CO > 4 || EPI == E_RES || EPI == E_SUB || EPI == E_ADD,
+                "thin outputs are NCHW state tensors");
   static bool attr_set = false;
   static int max_blocks = 0;
   auto kern = conv_mfma_kernel<PREC, CI, CO, PRO, EPI>;

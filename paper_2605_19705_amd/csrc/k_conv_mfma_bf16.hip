@@ -19,6 +19,7 @@ int by_epi(const ConvArgs& a, hipStream_t s) {
 template <int CI, int CO>
 int thin(const ConvArgs& a, hipStream_t s) {
   if (a.epi == E_RES) return launch_shape<PREC_BF16, CI, CO, P_NONE, E_RES>(a, s);
+  if (a.epi == E_ADD) return launch_shape<PREC_BF16, CI, CO, P_NONE, E_ADD>(a, s);
   if (a.epi == E_SUB) return launch_shape<PREC_BF16, CI, CO, P_NONE, E_SUB>(a, s);
   return fail(IDQ_E_UNSUPPORTED, "no bf16 MFMA epilogue of this kind");
 }

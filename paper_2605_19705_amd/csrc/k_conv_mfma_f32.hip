@@ -21,6 +21,7 @@ template <int CI, int CO>
 int thin(const ConvArgs& a, hipStream_t s) {
   const bool jvp = a.pro == P_JVP;
   if (a.epi == E_RES && !jvp) return launch_shape<PREC_F32, CI, CO, P_NONE, E_RES>(a, s);
+  if (a.epi == E_ADD && !jvp) return launch_shape<PREC_F32, CI, CO, P_NONE, E_ADD>(a, s);
   if (a.epi == E_SUB) {
     if (jvp) return launch_shape<PREC_F32, CI, CO, P_JVP, E_SUB>(a, s);
     return launch_shape<PREC_F32, CI, CO, P_NONE, E_SUB>(a, s);

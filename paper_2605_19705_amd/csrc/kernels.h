@@ -30,6 +30,7 @@ enum Epi {
   E_SUB = 3,    // out0 = e0 - acc                         (grad g = r - J^T r)
   E_RAW = 4,    // out0 = acc
   E_DDOT = 5,   // out0 = sigma''(h) e1 e2 + sigma'(h) acc, out1 = sigma'(h) e2  (e0 = a)
+  E_ADD = 6,    // out0 = e0 + (acc + b)                   (x0 = y + W(y))
 };
 
 enum Fmt { F_NCHW = 0, F_NHWC = 1 };
