@@ -11,8 +11,11 @@ One step = one i-DEQ solve of the whole batch until every image reaches
 
 Two arms are timed:
   headline  bf16 matrix-core convs (fp32 accumulate) until rel < 1e-3 or
-            stagnation, then fp32 refinement to 1e-4, started from the learned
-            warm start when its weights are available (else from y),
+            stagnation, then split-bf16 convs (each float operand as bf16
+            hi + lo, three products) to rel < 1e-4, then fp32 convs until an
+            fp32 update has rel < 1e-4 (--refine f32 skips the split phase);
+            started from the learned warm start when its weights are
+            available (else from y),
   fp32      fp32 matrix-core convs from x0 = y ("FP32 plain").
 Prints one JSON line (value = headline images/s).
 """
@@ -29,6 +32,24 @@ METRIC = "restored 256^2 images/s at rel. residual 1e-4: BF16+warm-start vs FP32
 BF16_PEAK = 2.5e15     # MI355X dense bf16 matrix-core peak, FLOP/s
 F32_PEAK = 157.3e12    # MI355X dense fp32 matrix-core peak, FLOP/s
 FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
+# HBM bytes per launch of the bf16 64->64 conv kernel in this solve, from the
+# FETCH_SIZE / WRITE_SIZE counter runs summarised in
+# profiles/conv_bf16_64x64_deblur_8x3x256_hbm_counters.md (FETCH x 2.0, WRITE x 1.0,
+# the factors a 256 MiB device copy gives); valid only while the kernel's device
+# code is the one measured (sha256 of its two sources below), else reported as null.
+TRAFFIC_BYTES_PER_LAUNCH = 121805 * 1024
+TRAFFIC_SOURCES = ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
+                   "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")
+TRAFFIC_SHA256 = "4241daf86a97debd65c342a4d9b80d7154e16d8a45ed48bd9c78cee94e760f94"
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -55,7 +76,7 @@ def time_arm(torch, ctx, y, K, W, profile=False, **kw):
     torch.cuda.synchronize()
     if profile:
         ctx.profile(True)
-    times, iters, low = [], [], []
+    times, iters, low, mid = [], [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(K):
@@ -65,12 +86,14 @@ def time_arm(torch, ctx, y, K, W, profile=False, **kw):
         times.append(time.perf_counter() - t0)
         iters.append(res.iters.tolist())
         low.append(res.iters_low.tolist())
+        mid.append(res.iters_mid.tolist())
         assert (res.status == 0).all(), f"solve did not converge: {res.status}"
     total = time.perf_counter() - t_all
     prof = ctx.profile_read() if profile else None
     if profile:
         ctx.profile(False)
-    return dict(total_s=total, step_s=times, iters=iters, iters_low=low, prof=prof, x=x)
+    return dict(total_s=total, step_s=times, iters=iters, iters_low=low, iters_mid=mid, prof=prof,
+                x=x)
 
 
 def cpu_baseline(iters_per_image, sample_iters=3):
@@ -108,7 +131,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-plain arm")
-    ap.add_argument("--ws-weights", default=None, help="warm-start weights (.npy, float64)")
+    ap.add_argument("--refine", default="bf16x3", choices=["f32", "bf16x3"],
+                    help="bf16x3: a split-bf16 phase between the bf16 phase and the float32 "
+                         "updates that end every solve; f32: straight to float32")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy a buffer of this many MiB device-to-device (a plain copy "
+                         "kernel of known size, for scaling hardware byte counters)")
+    ap.add_argument("--ws-weights", default=os.path.join(ROOT, "paper_2605_19705_amd", "weights",
+                                                         "warmstart_deblur.npy"),
+                    help="trained warm-start parameters (.npy, packed [W_1, b_1, ...])")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the per-image solves need no exchange, so more "
@@ -119,6 +150,15 @@ def main():
     import numpy as np
     import torch
     import synth
+
+    if args.copy_probe > 0:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe of {nbytes} bytes done")
+        del src, dst
 
     log("bench: building the deblurring problem (8x3x256x256)")
     ctx, y, layers, taps, xt, nz = make_problem(torch)
@@ -135,9 +175,10 @@ def main():
     init = "y"
     if args.ws_weights and os.path.exists(args.ws_weights):
         from paper_2605_19705_amd import WarmStart
-        ws = WarmStart(np.load(args.ws_weights), device=0)
+        ws = WarmStart(np.load(args.ws_weights).astype(np.float64), device=0)
         init = "warmstart"
-    head_kw = dict(common, conv_prec="bf16", switch_tol=1e-3, switch_patience=10, init=init, ws=ws)
+    head_kw = dict(common, conv_prec="bf16", switch_tol=1e-3, switch_patience=10, init=init, ws=ws,
+                   ws_prec="bf16", refine_prec=args.refine)
 
     log(f"bench: headline arm (bf16 + fp32 refinement, init={init}), "
         f"{args.warmup} warmup + {args.steps} timed solves")
@@ -161,7 +202,9 @@ def main():
     flops_per_launch = FLOP_PER_PX_64 * px / max(launches, 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) if launches else 0.0
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK,
+                "traffic": TRAFFIC_BYTES_PER_LAUNCH if sources_sha256() == TRAFFIC_SHA256 else None,
+                "traffic_unit": "bytes per launch",
                 "kernel": "conv_mfma_kernel<bf16, 64, 64>", "launches": launches,
                 "avg_launch_us": avg_ms * 1e3,
                 "flop_per_launch": flops_per_launch}
@@ -189,12 +232,15 @@ def main():
         "config": {
             "workload": "i-DEQ deblurring, 8x3x256x256, circular 9x9 gaussian (sigma 1.6), "
                         "noise 0.01, 5-layer 64-channel softplus regularizer, rel. residual 1e-4",
-            "arm": f"bf16 convs + fp32 refinement, init={init}",
+            "arm": ("bf16 convs, then split-bf16 (hi/lo, 3 products) convs to rel 1e-4, then "
+                    "fp32 convs until an fp32 update has rel < 1e-4" if args.refine == "bf16x3"
+                    else "bf16 convs, then fp32 convs to rel 1e-4") + f"; init={init}",
             "global_batch": n_img,
             "parallelism": "single GPU",
         },
         "iters_per_image": head["iters"][-1],
         "bf16_iters_per_image": head["iters_low"][-1],
+        "split_iters_per_image": head["iters_mid"][-1],
         "fp32_plain": None if fp32 is None else {
             "value": fp32["value"], "iters_per_image": fp32["iters"][-1],
             "ms_per_step": 1e3 * fp32["total_s"] / len(fp32["step_s"])},

@@ -47,6 +47,11 @@ extern "C" {
 #define IDQ_F64   0
 #define IDQ_F32   1
 #define IDQ_BF16  2   /* conv arithmetic only: bf16 operands, fp32 accumulate */
+#define IDQ_BF16X3 3  /* conv arithmetic only: each float32 operand split into bf16
+                         hi + lo parts, three bf16 products per term (hi*hi + lo*hi +
+                         hi*lo) accumulated in fp32 -- products good to ~2^-16
+                         relative; float32 activations.  Layers without a split
+                         kernel (image-facing ones) run in IDQ_F32. */
 
 /* ---- activations, operators, options ------------------------------------ */
 #define IDQ_ACT_SOFTPLUS   0
@@ -107,7 +112,8 @@ typedef struct {
     int    fixed_iters;     /* > 0: exactly this many updates, tol ignored       */
     double restart_B;       /* restart threshold B (eq. restart); <= 0 => off    */
     int    grad_at;         /* IDQ_GRAD_AT_*                                     */
-    int    conv_prec;       /* IDQ_F64 (dtype F64 only) | IDQ_F32 | IDQ_BF16      */
+    int    conv_prec;       /* IDQ_F64 (dtype F64 only) | IDQ_F32 | IDQ_BF16 |
+                               IDQ_BF16X3                                         */
     double switch_tol;      /* BF16 phase ends when rel < switch_tol ...          */
     int    switch_patience; /* ... or after this many BF16 steps with no new best */
     int    power_iters;     /* power iterations when tau == 0                    */
@@ -116,7 +122,11 @@ typedef struct {
     int    init;            /* IDQ_INIT_* used when x0 == NULL                    */
     idq_ws* ws;             /* warm-start network for IDQ_INIT_WARMSTART          */
     int    ws_prec;         /* IDQ_F32 | IDQ_BF16 for the warm-start inference    */
-    int    use_graph;       /* 1: replay captured HIP graphs of the iteration     */
+    int    refine_prec;     /* with conv_prec == IDQ_BF16: IDQ_F32 (default): the
+                               BF16 phase hands over to float32; IDQ_BF16X3: to a
+                               split-bf16 phase that runs until rel < tol (or
+                               stagnates), then float32 updates until rel < tol.
+                               An image stops only on a float32 update.          */
     double* rel_history;    /* host, nullable: n * history_len doubles; entry
                                [k * n + i] = relative residual of image i after
                                update k+1 (NaN once the image has stopped)        */
@@ -131,6 +141,7 @@ typedef struct {
     int    status;          /* IDQ_ST_*                                            */
     double rel;             /* last relative residual ||x^{k+1}-x^k|| / ||x^k||    */
     double tau;             /* step size used                                      */
+    int    iters_mid;       /* of which in the split-bf16 phase                    */
 } idq_solve_info;
 
 #define IDQ_BWD_JFB       0   /* Jacobian-free backprop: adjoint u = v           */
@@ -223,6 +234,7 @@ int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_d
 #define IDQ_PROF_STENCIL       3   /* blur stencils of grad f                    */
 #define IDQ_PROF_UPDATE        4   /* extrapolation, update, finalize            */
 #define IDQ_PROF_WARMSTART     5   /* warm-start network inference               */
+#define IDQ_PROF_CONV64_BF16X3 6   /* 64->64-channel conv passes, split-bf16 MFMA */
 /* Enable (on != 0) or disable accounting; resets all counters.  Synchronous. */
 int idq_profile_enable(idq_ctx* ctx, int on);
 /* Totals since the last enable: summed device time (ms), number of launches

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libidq.so")
 
 IDQ_OK, IDQ_W_MAXITER = 0, 1
 IDQ_E_INVAL, IDQ_E_NOMEM, IDQ_E_HIP, IDQ_E_NONFINITE, IDQ_E_UNSUPPORTED = -1, -2, -3, -4, -5
-IDQ_F64, IDQ_F32, IDQ_BF16 = 0, 1, 2
+IDQ_F64, IDQ_F32, IDQ_BF16, IDQ_BF16X3 = 0, 1, 2, 3
 IDQ_ACT_SOFTPLUS, IDQ_ACT_IDENTITY = 0, 1
 IDQ_OP_IDENTITY, IDQ_OP_BLUR_CIRC, IDQ_OP_TANH_BLUR = 0, 1, 2
 IDQ_GRAD_AT_EXTRAPOLATED, IDQ_GRAD_AT_CURRENT = 0, 1
@@ -22,7 +22,7 @@ IDQ_MAX_LAYERS = 8
 IDQ_ST_CONVERGED, IDQ_ST_MAXITER, IDQ_ST_FIXED, IDQ_ST_NONFINITE = 0, 1, 2, -4
 IDQ_BWD_JFB, IDQ_BWD_IMPLICIT = 0, 1
 PROF_CLASSES = {"conv64_bf16": 0, "conv64_f32": 1, "conv_other": 2, "stencil": 3, "update": 4,
-                "warmstart": 5}
+                "warmstart": 5, "conv64_bf16x3": 6}
 
 EXPORTED = [
     "idq_last_error", "idq_version", "idq_solve_opts_default", "idq_create", "idq_destroy",
@@ -51,13 +51,14 @@ class SolveOpts(C.Structure):
                 ("switch_tol", C.c_double), ("switch_patience", C.c_int),
                 ("power_iters", C.c_int), ("power_v0", C.c_void_p), ("poll_every", C.c_int),
                 ("init", C.c_int), ("ws", C.c_void_p), ("ws_prec", C.c_int),
-                ("use_graph", C.c_int), ("rel_history", C.POINTER(C.c_double)),
+                ("refine_prec", C.c_int), ("rel_history", C.POINTER(C.c_double)),
                 ("history_len", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("iters_low", C.c_int), ("restarts", C.c_int),
-                ("status", C.c_int), ("rel", C.c_double), ("tau", C.c_double)]
+                ("status", C.c_int), ("rel", C.c_double), ("tau", C.c_double),
+                ("iters_mid", C.c_int)]
 
 
 class BwdOpts(C.Structure):

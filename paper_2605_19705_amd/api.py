@@ -15,8 +15,9 @@ import torch
 
 from . import _lib as L
 
-_PREC = {"f64": L.IDQ_F64, "f32": L.IDQ_F32, "bf16": L.IDQ_BF16,
-         L.IDQ_F64: L.IDQ_F64, L.IDQ_F32: L.IDQ_F32, L.IDQ_BF16: L.IDQ_BF16}
+_PREC = {"f64": L.IDQ_F64, "f32": L.IDQ_F32, "bf16": L.IDQ_BF16, "bf16x3": L.IDQ_BF16X3,
+         L.IDQ_F64: L.IDQ_F64, L.IDQ_F32: L.IDQ_F32, L.IDQ_BF16: L.IDQ_BF16,
+         L.IDQ_BF16X3: L.IDQ_BF16X3}
 _OPS = {"identity": L.IDQ_OP_IDENTITY, "blur": L.IDQ_OP_BLUR_CIRC, "tanh_blur": L.IDQ_OP_TANH_BLUR}
 
 
@@ -59,6 +60,7 @@ def pack_layers(layers):
 class SolveResult:
     iters: np.ndarray
     iters_low: np.ndarray
+    iters_mid: np.ndarray
     restarts: np.ndarray
     status: np.ndarray
     rel: np.ndarray
@@ -184,7 +186,7 @@ class IDQ:
     def solve(self, y, x0=None, out=None, beta=0.5, tau=0.0, lam=1.0, tol=1e-4, max_iter=1000,
               fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
               switch_tol=1e-3, switch_patience=10, power_iters=30, power_v0=None,
-              poll_every=8, init="y", ws=None, ws_prec="bf16", use_graph=False,
+              poll_every=8, init="y", ws=None, ws_prec="bf16", refine_prec="f32",
               history=0):
         o = L.SolveOpts()
         L.lib().idq_solve_opts_default(C.byref(o))
@@ -201,7 +203,7 @@ class IDQ:
                   "warmstart": L.IDQ_INIT_WARMSTART}[init]
         o.ws = ws._h.value if ws is not None else None
         o.ws_prec = _PREC[ws_prec]
-        o.use_graph = int(bool(use_graph))
+        o.refine_prec = _PREC[refine_prec]
         n = y.shape[0]
         hist = None
         if history:
@@ -215,6 +217,7 @@ class IDQ:
         L.check(code, allow=(L.IDQ_OK, L.IDQ_W_MAXITER, L.IDQ_E_NONFINITE))
         res = SolveResult(iters=np.array([i.iters for i in info]),
                           iters_low=np.array([i.iters_low for i in info]),
+                          iters_mid=np.array([i.iters_mid for i in info]),
                           restarts=np.array([i.restarts for i in info]),
                           status=np.array([i.status for i in info]),
                           rel=np.array([i.rel for i in info]),
@@ -277,13 +280,17 @@ class IDQSolve(torch.autograd.Function):
 class WarmStart:
     """Learned initial iterate x0 = y + W_phi(y) (``idq_ws_*`` of the C ABI).
 
-    ``layers``: the 9 (W, b) pairs of the encoder-decoder, float64 arrays.
-    Images are float32 CUDA tensors of shape (n, 3, h, w) with h, w even.
+    ``layers``: the 9 (W, b) pairs of the encoder-decoder, or the flat packed
+    parameter vector [W_1, b_1, ..., W_9, b_9].  Images are float32 CUDA
+    tensors of shape (n, 3, h, w) with h, w even.
     """
 
     def __init__(self, layers, device=0):
         lib = L.lib()
-        flat = np.ascontiguousarray(pack_layers(layers))
+        if isinstance(layers, np.ndarray) and layers.ndim == 1:
+            flat = np.ascontiguousarray(layers, dtype=np.float64)
+        else:
+            flat = np.ascontiguousarray(pack_layers(layers))
         n = int(lib.idq_ws_num_params())
         if flat.size != n:
             raise ValueError(f"warm-start network takes {n} parameters, got {flat.size}")

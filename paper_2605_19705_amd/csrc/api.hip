@@ -48,7 +48,7 @@ void Workspace::release() {
   }
 }
 
-int Profiler::begin(int cls, hipStream_t s, ProfRec* r) {
+int Profiler::take(int cls, ProfRec* r) {
   r->cls = cls;
   for (hipEvent_t* e : {&r->e0, &r->e1}) {
     if (!pool.empty()) {
@@ -58,6 +58,11 @@ int Profiler::begin(int cls, hipStream_t s, ProfRec* r) {
       IDQ_HIP(hipEventCreate(e));
     }
   }
+  return IDQ_OK;
+}
+
+int Profiler::begin(int cls, hipStream_t s, ProfRec* r) {
+  IDQ_TRY(take(cls, r));
   IDQ_HIP(hipEventRecord(r->e0, s));
   return IDQ_OK;
 }
@@ -92,17 +97,30 @@ void Profiler::release() {
 
 namespace {
 
+// Arithmetic a layer pass actually runs in: split-bf16 only where a split
+// kernel exists, float32 (same float activations) elsewhere.
+int eff_prec(int prec, int ci, int co) {
+  return (prec == PREC_SPLIT && !mfma_supported(PREC_SPLIT, ci, co)) ? PREC_F32 : prec;
+}
+
 // Launch a conv pass, with device-time accounting when profiling is on.
 int run_conv(idq_ctx* ctx, ConvArgs a, int prec, hipStream_t s) {
+  prec = eff_prec(prec, a.CI, a.CO);
   if (!ctx->prof.on) return launch_conv(a, prec, s);
   int cls = PC_CONV_OTHER;
   if (a.CI == 64 && a.CO == 64 && prec != PREC_F64)
-    cls = prec == PREC_BF16 ? PC_CONV_WIDE_BF16 : PC_CONV_WIDE_F32;
+    cls = prec == PREC_BF16 ? PC_CONV_WIDE_BF16
+                            : (prec == PREC_SPLIT ? PC_CONV_WIDE_SPLIT : PC_CONV_WIDE_F32);
   a.work_px = ctx->prof.dev_px + cls;
+  // the launcher stamps the events from the dispatch itself (hipExtLaunchKernel)
+  // so that they time the kernel alone, not its launch latency
   ProfRec r;
-  IDQ_TRY(ctx->prof.begin(cls, s, &r));
+  IDQ_TRY(ctx->prof.take(cls, &r));
+  a.ev0 = r.e0;
+  a.ev1 = r.e1;
   IDQ_TRY(launch_conv(a, prec, s));
-  return ctx->prof.end(r, s);
+  ctx->prof.pending.push_back(r);
+  return IDQ_OK;
 }
 
 template <class F>
@@ -115,7 +133,7 @@ int profiled(idq_ctx* ctx, int cls, hipStream_t s, F&& f) {
 }
 
 size_t math_size(int prec) { return prec == PREC_F64 ? 8 : 4; }
-size_t act_size(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
+size_t act_size(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_BF16 ? 2 : 4); }
 
 int upload(void** dst, const void* src, size_t bytes) {
   IDQ_HIP(hipMalloc(dst, bytes));
@@ -125,7 +143,7 @@ int upload(void** dst, const void* src, size_t bytes) {
 
 void free_layers(idq_ctx* ctx) {
   for (auto& L : ctx->layers)
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < kNumPrec; ++p) {
       void** all[] = {&L.fwd[p], &L.tr[p], &L.bias[p], &L.fwd_mfma[p], &L.tr_mfma[p]};
       for (void** q : all)
         if (*q) {
@@ -183,6 +201,22 @@ int pack_weights(idq_ctx* ctx) {
         IDQ_TRY(upload(&lw.tr_mfma[prec], buf.data(), buf.size()));
       }
     }
+    // split-bf16: hi/lo fragment copies where a split kernel exists, float bias
+    {
+      std::vector<float> fb(co);
+      for (int o = 0; o < co; ++o) fb[o] = static_cast<float>(b[o]);
+      IDQ_TRY(upload(&lw.bias[PREC_SPLIT], fb.data(), co * 4));
+      if (mfma_supported(PREC_SPLIT, ci, co)) {
+        std::vector<char> buf(pack_mfma_weights(PREC_SPLIT, ci, co, W, nullptr));
+        pack_mfma_weights(PREC_SPLIT, ci, co, W, buf.data());
+        IDQ_TRY(upload(&lw.fwd_mfma[PREC_SPLIT], buf.data(), buf.size()));
+      }
+      if (mfma_supported(PREC_SPLIT, co, ci)) {
+        std::vector<char> buf(pack_mfma_weights(PREC_SPLIT, co, ci, Wt.data(), nullptr));
+        pack_mfma_weights(PREC_SPLIT, co, ci, Wt.data(), buf.data());
+        IDQ_TRY(upload(&lw.tr_mfma[PREC_SPLIT], buf.data(), buf.size()));
+      }
+    }
   }
   return IDQ_OK;
 }
@@ -217,8 +251,8 @@ int check_prec(int dtype, int prec) {
   if (dtype != IDQ_F64 && dtype != IDQ_F32) return fail(IDQ_E_INVAL, "dtype must be IDQ_F64 or IDQ_F32");
   if (dtype == IDQ_F64 && prec != IDQ_F64)
     return fail(IDQ_E_INVAL, "float64 tensors need float64 conv arithmetic");
-  if (dtype == IDQ_F32 && prec != IDQ_F32 && prec != IDQ_BF16)
-    return fail(IDQ_E_INVAL, "float32 tensors need F32 or BF16 conv arithmetic");
+  if (dtype == IDQ_F32 && prec != IDQ_F32 && prec != IDQ_BF16 && prec != IDQ_BF16X3)
+    return fail(IDQ_E_INVAL, "float32 tensors need F32, BF16 or BF16X3 conv arithmetic");
   return IDQ_OK;
 }
 
@@ -232,6 +266,7 @@ ConvArgs conv_base(const idq_ctx* ctx, const Geometry& g, int l, bool transposed
                    const int* gate, int mask) {
   ConvArgs a{};
   const LayerW& lw = ctx->layers[l];
+  prec = transposed ? eff_prec(prec, lw.co, lw.ci) : eff_prec(prec, lw.ci, lw.co);
   a.NI = g.NI;
   a.H = g.h;
   a.W = g.w;
@@ -547,6 +582,8 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   Geometry g;
   IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
   IDQ_TRY(check_prec(dtype, o->conv_prec));
+  if (o->conv_prec == IDQ_BF16 && o->refine_prec != IDQ_F32 && o->refine_prec != IDQ_BF16X3)
+    return fail(IDQ_E_INVAL, "refine_prec must be IDQ_F32 or IDQ_BF16X3");
   if (o->max_iter <= 0 && o->fixed_iters <= 0) return fail(IDQ_E_INVAL, "max_iter must be positive");
   const bool use_net = ctx->L > 0 && o->lambda != 0.0;
   const size_t es = elem_size(dtype);
@@ -580,7 +617,9 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     IDQ_HIP(hipMemsetAsync(xb[0], 0, sbytes, s));
   } else if (o->init == IDQ_INIT_WARMSTART) {
     if (!o->ws || dtype != IDQ_F32) return fail(IDQ_E_INVAL, "warm start needs a network and float32");
-    IDQ_TRY(ws_forward_internal(o->ws, y, xb[0], n, c, h, w, o->ws_prec, s));
+    IDQ_TRY(profiled(ctx, PC_WARMSTART, s, [&] {
+      return ws_forward_internal(o->ws, y, xb[0], n, c, h, w, o->ws_prec, s);
+    }));
   } else {
     return fail(IDQ_E_INVAL, "bad init");
   }
@@ -589,7 +628,8 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   double tau = o->tau;
   if (tau <= 0.0) {
     if (!o->power_v0) return fail(IDQ_E_INVAL, "tau == 0 needs power_v0");
-    const int pprec = o->conv_prec == IDQ_BF16 ? IDQ_F32 : o->conv_prec;
+    const int pprec = (o->conv_prec == IDQ_BF16 || o->conv_prec == IDQ_BF16X3) ? IDQ_F32
+                                                                               : o->conv_prec;
     double L = 0.0;
     IDQ_TRY(power_iteration(ctx, g, dtype, pprec, xb[0], y, o->power_v0, o->lambda,
                             o->power_iters > 0 ? o->power_iters : 30, &L, s));
@@ -615,8 +655,11 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
 
   const int limit = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
   const int poll = o->poll_every > 0 ? o->poll_every : 8;
-  const int final_prec = o->conv_prec == IDQ_BF16 ? IDQ_F32 : o->conv_prec;
-  bool low_live = o->conv_prec == IDQ_BF16;
+  // bf16 start: bf16 -> [split-bf16 if refine_prec says so] -> float32
+  const bool bf_start = o->conv_prec == IDQ_BF16;
+  const bool use_mid = bf_start && o->refine_prec == IDQ_BF16X3;
+  const int final_prec = bf_start ? IDQ_F32 : o->conv_prec;
+  bool low_live = bf_start, mid_live = use_mid;
   const int* gp = static_cast<const int*>(gate);
   const bool identity = ctx->op_kind == IDQ_OP_IDENTITY;
 
@@ -634,6 +677,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   fa.switch_patience = o->switch_patience > 0 ? o->switch_patience : 10;
   fa.max_iter = o->max_iter;
   fa.fixed_iters = o->fixed_iters;
+  fa.use_mid = use_mid ? 1 : 0;
 
   int t = 0;
   while (t < limit) {
@@ -647,7 +691,9 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
       const void* p = o->grad_at == IDQ_GRAD_AT_CURRENT ? xa : z;
       if (!identity) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false));
       if (use_net) {
+        // phases only advance, so a phase absent at the last poll stays absent
         if (low_live) IDQ_TRY(net_grad(ctx, g, IDQ_BF16, p, q, gp, 1 << G_LOW, s));
+        if (mid_live) IDQ_TRY(net_grad(ctx, g, IDQ_BF16X3, p, q, gp, 1 << G_MID, s));
         IDQ_TRY(net_grad(ctx, g, final_prec, p, q, gp, 1 << G_FINAL, s));
       }
       UpdateArgs ua{};
@@ -676,12 +722,14 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     IDQ_HIP(hipMemcpyAsync(ctx->host_gate, gate, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     IDQ_HIP(hipStreamSynchronize(s));
     if (ctx->prof.on) IDQ_TRY(ctx->prof.flush());
-    bool any = false, anylow = false;
+    bool any = false, anylow = false, anymid = false;
     for (int i = 0; i < n; ++i) {
       any |= ctx->host_gate[i] != G_DONE;
       anylow |= ctx->host_gate[i] == G_LOW;
+      anymid |= ctx->host_gate[i] == G_MID;
     }
     low_live = anylow;
+    mid_live = use_mid && (anylow || anymid);
     if (!any) break;
   }
   IDQ_TRY(launch_gather_result(xb[0], xb[1], x_out, static_cast<const ImgState*>(state), n, g.per,
@@ -695,6 +743,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   for (int i = 0; i < n; ++i) {
     info[i].iters = hs[i].it;
     info[i].iters_low = hs[i].it_low;
+    info[i].iters_mid = hs[i].it_mid;
     info[i].restarts = hs[i].restarts;
     info[i].status = hs[i].status;
     info[i].rel = hs[i].rel;
@@ -887,7 +936,7 @@ void idq_solve_opts_default(idq_solve_opts* o) {
   o->poll_every = 8;
   o->init = IDQ_INIT_Y;
   o->ws_prec = IDQ_BF16;
-  o->use_graph = 0;
+  o->refine_prec = IDQ_F32;
 }
 
 int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, int device) {
@@ -1115,7 +1164,8 @@ int idq_hvp(idq_ctx* ctx, const void* x, const void* y, const void* v, void* out
   return guarded([&]() -> int {
     if (!ctx || !x || !v || !out) return fail(IDQ_E_INVAL, "null argument");
     IDQ_TRY(check_prec(dtype, conv_prec));
-    if (conv_prec == IDQ_BF16) return fail(IDQ_E_UNSUPPORTED, "HVP is float32/float64 only");
+    if (conv_prec == IDQ_BF16 || conv_prec == IDQ_BF16X3)
+      return fail(IDQ_E_UNSUPPORTED, "HVP is float32/float64 only");
     Geometry g;
     IDQ_TRY(set_device(ctx));
     IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
@@ -1134,7 +1184,8 @@ int idq_lipschitz(idq_ctx* ctx, const void* x, const void* y, const void* v0, do
   return guarded([&]() -> int {
     if (!ctx || !x || !y || !v0 || !L) return fail(IDQ_E_INVAL, "null argument");
     IDQ_TRY(check_prec(dtype, conv_prec));
-    if (conv_prec == IDQ_BF16) return fail(IDQ_E_UNSUPPORTED, "HVP is float32/float64 only");
+    if (conv_prec == IDQ_BF16 || conv_prec == IDQ_BF16X3)
+      return fail(IDQ_E_UNSUPPORTED, "HVP is float32/float64 only");
     if (iters <= 0) return fail(IDQ_E_INVAL, "iters must be positive");
     Geometry g;
     IDQ_TRY(set_device(ctx));

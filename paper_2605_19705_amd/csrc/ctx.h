@@ -28,18 +28,20 @@ struct Workspace {
 
 struct LayerW {
   int ci = 0, co = 0;
-  // per precision (IDQ_F64/F32/BF16): direct forward and transposed weights
-  // [co][ci][9] / [ci][co][9] in the math type, bias [co], MFMA-packed copies.
-  void* fwd[3] = {};
-  void* tr[3] = {};
-  void* bias[3] = {};
-  void* fwd_mfma[3] = {};
-  void* tr_mfma[3] = {};
+  // per precision (IDQ_F64/F32/BF16/BF16X3): direct forward and transposed
+  // weights [co][ci][9] / [ci][co][9] in the math type, bias [co], MFMA-packed
+  // copies (BF16X3: MFMA copies and bias only).
+  void* fwd[kNumPrec] = {};
+  void* tr[kNumPrec] = {};
+  void* bias[kNumPrec] = {};
+  void* fwd_mfma[kNumPrec] = {};
+  void* tr_mfma[kNumPrec] = {};
 };
 
 // Optional device-time accounting of kernel classes (HIP events around launches).
 enum ProfClass { PC_CONV_WIDE_BF16 = 0, PC_CONV_WIDE_F32 = 1, PC_CONV_OTHER = 2, PC_STENCIL = 3,
-                 PC_UPDATE = 4, PC_WARMSTART = 5, PC_COUNT = 6 };
+                 PC_UPDATE = 4, PC_WARMSTART = 5,
+                 PC_CONV_WIDE_SPLIT = 6, PC_COUNT = 7 };
 struct ProfRec {
   int cls;
   hipEvent_t e0, e1;
@@ -51,7 +53,8 @@ struct Profiler {
   double ms[PC_COUNT] = {};
   long long launches[PC_COUNT] = {};
   unsigned long long* dev_px = nullptr;  // device counters, one per class
-  int begin(int cls, hipStream_t s, ProfRec* r);
+  int take(int cls, ProfRec* r);                   // events only
+  int begin(int cls, hipStream_t s, ProfRec* r);   // take + record the start
   int end(ProfRec& r, hipStream_t s);
   int flush();
   void release();

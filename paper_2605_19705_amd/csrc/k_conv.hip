@@ -141,11 +141,18 @@ static int force_direct() {
 
 int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
   if (a.NI <= 0 || a.H <= 0 || a.W <= 0) return IDQ_OK;
+  if (prec == PREC_SPLIT) {
+    // no direct-kernel form: callers run shapes without a split kernel as PREC_F32
+    if (!a.wmfma || !mfma_supported(prec, a.CI, a.CO) || !mfma_form_ok(a, prec))
+      return fail(IDQ_E_UNSUPPORTED, "split-bf16 conv pass of an unsupported form");
+    return launch_conv_mfma(a, prec, s);
+  }
   if (prec != PREC_F64 && a.wmfma && !force_direct() && mfma_supported(prec, a.CI, a.CO) &&
       mfma_form_ok(a, prec))
     return launch_conv_mfma(a, prec, s);
   dim3 grid((a.H * a.W + 255) / 256, a.NI, (a.CO + 15) / 16);
   if (grid.y > 65535) return fail(IDQ_E_INVAL, "too many images in one conv pass");
+  if (a.ev0) IDQ_HIP(hipEventRecord(a.ev0, s));
   switch (prec) {
     case PREC_F64:
       conv_direct_kernel<double, double, double, false><<<grid, 256, 0, s>>>(a);
@@ -160,6 +167,7 @@ int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
       return fail(IDQ_E_INVAL, "bad conv precision");
   }
   IDQ_HIP(hipGetLastError());
+  if (a.ev1) IDQ_HIP(hipEventRecord(a.ev1, s));
   return IDQ_OK;
 }
 

@@ -29,6 +29,8 @@
 // from a per-pixel 4-channel LDS tile.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace idq {
@@ -45,9 +47,13 @@ constexpr int RW = 4;  // output rows per wave
 
 template <int PREC, int CI, int CO>
 struct Cfg {
-  static constexpr bool BF = PREC == PREC_BF16;
-  static constexpr int ES = BF ? 2 : 4;        // LDS element bytes
-  static constexpr int V = BF ? 8 : 4;         // k elements per lane per chunk (16 bytes)
+  static constexpr bool BF = PREC == PREC_BF16;      // bf16 activations in HBM
+  static constexpr bool SPLIT = PREC == PREC_SPLIT;  // float activations, hi/lo bf16 operands
+  static constexpr bool MBF = BF || SPLIT;           // bf16 matrix-core operands
+  static constexpr int GES = BF ? 2 : 4;       // HBM activation element bytes
+  static constexpr int GV = 16 / GES;          // HBM elements per 16-byte load
+  static constexpr int ES = MBF ? 2 : 4;       // LDS element bytes
+  static constexpr int V = MBF ? 8 : 4;        // k elements per lane per chunk (16 bytes)
   static constexpr int KC = 4 * V;             // k per chunk
   static constexpr int K = 9 * CI;
   static constexpr int NCH = (K + KC - 1) / KC;
@@ -56,18 +62,24 @@ struct Cfg {
   static constexpr bool ROWS = (CI % KC) == 0;  // chunks align with taps: reuse rows
   static constexpr int CPT = ROWS ? CI / KC : 0;  // chunks per tap
   static constexpr int CIP = VEC ? CI : 4;
-  static constexpr int PIXB = CIP * ES + (VEC ? 16 : 0);
+  // split: a pixel holds the hi parts of its channels, then the lo parts
+  static constexpr int LO_OFF = CIP * ES;
+  static constexpr int PIXB = (SPLIT ? 2 : 1) * CIP * ES + (VEC ? 16 : 0);
   static constexpr int LDS_IN = (NPIX * PIXB + 15) / 16 * 16;
-  static constexpr bool WLDS = BF;
+  static constexpr bool WLDS = MBF;            // (split: the hi fragments; lo from L2)
   static constexpr int WBYTES = NCH * NJ * 64 * 16;
   static constexpr int LDS = LDS_IN + (WLDS ? WBYTES : 0);
   // prefetch: 16-byte items (VEC) or floats (gather) per thread for one tile
-  static constexpr int VPP = VEC ? CI / V : 0;
+  static constexpr int VPP = VEC ? CI / GV : 0;
   static constexpr int ITEMS = VEC ? (NPIX * VPP + kThreads - 1) / kThreads
                                    : (NPIX * CI + kThreads - 1) / kThreads;
   // fp32 reads its weights from global memory: a short unroll keeps the
   // hoisted loads within the register file
-  static constexpr int UNROLL = BF ? NCH : 2;
+  static constexpr int UNROLL = MBF ? NCH : 2;
+  // (dx, chunk) groups of the row-reuse loop unrolled at once: all of them for
+  // bf16; one for split operands, whose doubled fragments would spill otherwise
+  static constexpr int RUNROLL = BF ? 3 * CPT : 1;
+  static_assert(!SPLIT || (VEC && ROWS), "split operands need whole K chunks per tap");
 };
 
 __device__ inline unsigned pack2(bf16 lo, bf16 hi) {
@@ -120,7 +132,7 @@ __device__ inline void load_tile(const ConvArgs& a, Prefetch<C, PRO>& pf, int ni
         const int ly = p / HW_, lx = p - (p / HW_) * HW_;
         const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
         if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
-          const size_t e = (((static_cast<size_t>(ni) * a.H + gy) * a.W + gx) * CI + v * C::V) * C::ES;
+          const size_t e = (((static_cast<size_t>(ni) * a.H + gy) * a.W + gx) * CI + v * C::GV) * C::GES;
           val = *reinterpret_cast<const u32x4_t*>(static_cast<const char*>(a.in0) + e);
           if (PRO == P_JVP) hd = *reinterpret_cast<const u32x4_t*>(static_cast<const char*>(a.in1) + e);
         }
@@ -172,7 +184,19 @@ __device__ inline void store_tile(const ConvArgs& a, const Prefetch<C, PRO>& pf,
               val[q] = f2u((sp ? dsp_from_a(u2f(val[q])) : 1.f) * u2f(hd[q]));
           }
         }
-        *reinterpret_cast<u32x4_t*>(lin + p * C::PIXB + v * 16) = val;
+        if (C::SPLIT) {
+          // 4 floats -> bf16 hi parts and the bf16-rounded remainders x - hi
+          const unsigned h01 = pk_bf16(u2f(val[0]), u2f(val[1]));
+          const unsigned h23 = pk_bf16(u2f(val[2]), u2f(val[3]));
+          const unsigned l01 = pk_bf16(u2f(val[0]) - u2f(h01 << 16),
+                                       u2f(val[1]) - u2f(h01 & 0xffff0000u));
+          const unsigned l23 = pk_bf16(u2f(val[2]) - u2f(h23 << 16),
+                                       u2f(val[3]) - u2f(h23 & 0xffff0000u));
+          *reinterpret_cast<uint2*>(lin + p * C::PIXB + v * 8) = uint2{h01, h23};
+          *reinterpret_cast<uint2*>(lin + p * C::PIXB + C::LO_OFF + v * 8) = uint2{l01, l23};
+        } else {
+          *reinterpret_cast<u32x4_t*>(lin + p * C::PIXB + v * 16) = val;
+        }
       }
     } else {
       if (it < NPIX * CI) {
@@ -189,7 +213,7 @@ __device__ inline void store_tile(const ConvArgs& a, const Prefetch<C, PRO>& pf,
 
 template <class C>
 __device__ inline void mma(f32x4_t& acc, const u32x4_t& af, const u32x4_t& bf) {
-  if (C::BF) {
+  if (C::MBF) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, af),
                                                   __builtin_bit_cast(bf16x8_t, bf), acc, 0, 0, 0);
   } else {
@@ -203,6 +227,7 @@ template <int PREC, int CI, int CO, int PRO, int EPI>
 __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int ntx, int nty,
                                                                int ntiles) {
   using C = Cfg<PREC, CI, CO>;
+  static_assert(!C::SPLIT || PRO == P_NONE, "split passes take plain operands");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   char* lin = smem;
   const u32x4_t* lw = reinterpret_cast<const u32x4_t*>(smem + C::LDS_IN);
@@ -212,6 +237,13 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
   const bool sp = a.act == IDQ_ACT_SOFTPLUS;
   const int tiles_per_img = ntx * nty;
   auto open = [&](int t) { return gate_open(a.gate, a.gate_mask, (t / tiles_per_img) / a.img_div); };
+
+  // first open tile of this workgroup (uniform across it); a workgroup with
+  // none leaves before staging weights, so a pass whose images are all in
+  // another precision phase costs little more than its launch
+  int t = blockIdx.x;
+  while (t < ntiles && !open(t)) t += gridDim.x;
+  if (t >= ntiles) return;
 
   if (C::WLDS) {
     u32x4_t* dst = reinterpret_cast<u32x4_t*>(smem + C::LDS_IN);
@@ -231,10 +263,8 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       }
   }
 
-  int t = blockIdx.x;
-  while (t < ntiles && !open(t)) t += gridDim.x;
   Prefetch<C, PRO> pf;
-  if (t < ntiles) {
+  {
     const int ni = t / tiles_per_img, rem = t - ni * tiles_per_img;
     load_tile<C, CI, PRO>(a, pf, ni, (rem / ntx) * TH, (rem % ntx) * TW, tid);
   }
@@ -291,36 +321,54 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       // next (dx, c, dy) group are fetched while the current group's MFMAs
       // run (for fp32 they come from L2, whose latency would otherwise stall
       // every group).
-      auto load_af = [&](u32x4_t* dst, int dxc, int dy) {
+      constexpr int NL = C::SPLIT ? C::NJ : 1;
+      const u32x4_t* gwl = gw + C::NCH * C::NJ * 64;  // split: lo fragments
+      auto load_af = [&](u32x4_t* dst, u32x4_t* dlo, int dxc, int dy) {
         const int ch = (dy * 3 + dxc / C::CPT) * C::CPT + dxc % C::CPT;
 #pragma unroll
         for (int j = 0; j < C::NJ; ++j) dst[j] = C::WLDS ? lw[(ch * C::NJ + j) * 64 + lane]
                                                       : gw[(ch * C::NJ + j) * 64 + lane];
+        if (C::SPLIT) {
+#pragma unroll
+          for (int j = 0; j < C::NJ; ++j) dlo[j] = gwl[(ch * C::NJ + j) * 64 + lane];
+        }
       };
-      u32x4_t afc[C::NJ], afn[C::NJ];
-      load_af(afc, 0, 0);
-#pragma unroll (C::BF ? 3 * C::CPT : 1)
+      u32x4_t afc[C::NJ], afn[C::NJ], alc[NL], aln[NL];
+      load_af(afc, alc, 0, 0);
+#pragma unroll C::RUNROLL
       for (int dxc = 0; dxc < 3 * C::CPT; ++dxc) {
         const int dx = dxc / C::CPT, c = dxc % C::CPT;
-        u32x4_t brow[RW + 2];
+        u32x4_t brow[RW + 2], browl[C::SPLIT ? RW + 2 : 1];
         const int coff = (c * C::KC + g * C::V) * C::ES;
 #pragma unroll
         for (int ir = 0; ir < RW + 2; ++ir) {
           const int pix = (wv * RW + ir) * HW_ + c16 + dx;
           brow[ir] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + coff);
+          if (C::SPLIT)
+            browl[ir] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + C::LO_OFF + coff);
         }
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
           if (dy < 2)
-            load_af(afn, dxc, dy + 1);
+            load_af(afn, aln, dxc, dy + 1);
           else if (dxc + 1 < 3 * C::CPT)
-            load_af(afn, dxc + 1, 0);
+            load_af(afn, aln, dxc + 1, 0);
 #pragma unroll
           for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], afc[j], brow[r + dy]);
+            for (int j = 0; j < C::NJ; ++j) {
+              if (C::SPLIT) {  // small terms first: lo*hi + hi*lo, then hi*hi
+                mma<C>(acc[r][j], afc[j], browl[r + dy]);
+                mma<C>(acc[r][j], alc[j], brow[r + dy]);
+              }
+              mma<C>(acc[r][j], afc[j], brow[r + dy]);
+            }
 #pragma unroll
           for (int j = 0; j < C::NJ; ++j) afc[j] = afn[j];
+          if (C::SPLIT) {
+#pragma unroll
+            for (int j = 0; j < C::NJ; ++j) alc[j] = aln[j];
+          }
         }
       }
     } else {
@@ -507,7 +555,15 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
   if (nt > 0x7fffffff) return fail(IDQ_E_INVAL, "too many tiles");
   const int ntiles = static_cast<int>(nt);
   const int grid = ntiles < max_blocks ? ntiles : max_blocks;
-  kern<<<grid, kThreads, C::LDS, s>>>(a, ntx, nty, ntiles);
+  if (a.ev0) {
+    ConvArgs ac = a;
+    int nx = ntx, ny = nty, ntl = ntiles;
+    void* args[] = {&ac, &nx, &ny, &ntl};
+    IDQ_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(kThreads),
+                               args, C::LDS, s, a.ev0, a.ev1, 0));
+  } else {
+    kern<<<grid, kThreads, C::LDS, s>>>(a, ntx, nty, ntiles);
+  }
   IDQ_HIP(hipGetLastError());
   return IDQ_OK;
 }
@@ -518,6 +574,8 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
 #define IDQ_MFMA_WIDE(X) \
   X(1, 16) X(16, 16) X(3, 64) X(64, 64) X(3, 32) X(32, 32) X(32, 64) X(64, 32) X(96, 32) X(32, 96)
 #define IDQ_MFMA_THIN(X) X(16, 1) X(64, 3) X(32, 3)
+// split (hi/lo bf16) instantiations: the channel counts that are whole K chunks
+#define IDQ_MFMA_SPLIT(X) X(64, 64) X(32, 32) X(32, 64) X(64, 32)
 
 }  // namespace mfma
 }  // namespace idq

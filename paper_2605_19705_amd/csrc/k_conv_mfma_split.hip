@@ -1,0 +1,32 @@
+// Split-bf16 instantiations of the implicit-GEMM conv (kernel in k_conv_mfma.h):
+// float activations, each operand taken as bf16 hi + lo parts on the matrix cores.
+#include "k_conv_mfma.h"
+
+namespace idq {
+namespace mfma {
+
+namespace {
+
+template <int CI, int CO>
+int by_epi(const ConvArgs& a, hipStream_t s) {
+  switch (a.epi) {
+    case E_ACT: return launch_shape<PREC_SPLIT, CI, CO, P_NONE, E_ACT>(a, s);
+    case E_DELTA: return launch_shape<PREC_SPLIT, CI, CO, P_NONE, E_DELTA>(a, s);
+    case E_RAW: return launch_shape<PREC_SPLIT, CI, CO, P_NONE, E_RAW>(a, s);
+    default: return fail(IDQ_E_UNSUPPORTED, "no split-bf16 MFMA epilogue of this kind");
+  }
+}
+
+}  // namespace
+
+int launch_split(const ConvArgs& a, hipStream_t s) {
+  if (a.pro != P_NONE) return fail(IDQ_E_UNSUPPORTED, "split passes take plain operands");
+#define X(A, B) \
+  if (a.CI == A && a.CO == B) return by_epi<A, B>(a, s);
+  IDQ_MFMA_SPLIT(X)
+#undef X
+  return fail(IDQ_E_UNSUPPORTED, "no split-bf16 MFMA instantiation for this shape");
+}
+
+}  // namespace mfma
+}  // namespace idq

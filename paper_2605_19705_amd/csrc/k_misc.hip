@@ -222,23 +222,35 @@ __global__ void finalize_kernel(FinalizeArgs a) {
       s.S = 0.0;
       s.restarts += 1;
     }
-    const bool low = s.prec == G_LOW;
-    if (low) {
-      s.it_low += 1;
+    // precision phases: bf16 until rel < switch_tol or no new best for
+    // switch_patience updates; then (optionally) split-bf16 until rel < tol or
+    // the same stagnation rule; then the final arithmetic, which stops the image
+    const bool low = s.prec == G_LOW, mid = s.prec == G_MID;
+    if (low || mid) {
+      if (low)
+        s.it_low += 1;
+      else
+        s.it_mid += 1;
       if (rel < s.best_rel) {
         s.best_rel = rel;
         s.stall = 0;
       } else {
         s.stall += 1;
       }
-      if (rel < a.switch_tol || s.stall >= a.switch_patience) s.prec = G_FINAL;
+      const bool next = low ? (rel < a.switch_tol || s.stall >= a.switch_patience)
+                            : (rel < a.tol || s.stall >= a.switch_patience);
+      if (next) {
+        s.prec = (low && a.use_mid) ? G_MID : G_FINAL;
+        s.best_rel = INFINITY;
+        s.stall = 0;
+      }
     }
     if (a.fixed_iters > 0) {
       if (s.it >= a.fixed_iters) {
         s.status = IDQ_ST_FIXED;
         s.done = 1;
       }
-    } else if (!low && rel < a.tol) {
+    } else if (!low && !mid && rel < a.tol) {
       s.status = IDQ_ST_CONVERGED;
       s.done = 1;
     } else if (s.it >= a.max_iter) {

@@ -10,7 +10,11 @@ namespace idq {
 //   PREC_F32 : float everywhere
 //   PREC_BF16: float state tensors, bfloat16 activations and operands,
 //              float accumulation
-enum Prec { PREC_F64 = IDQ_F64, PREC_F32 = IDQ_F32, PREC_BF16 = IDQ_BF16 };
+//   PREC_SPLIT: float state tensors and activations; the 64-channel passes split
+//              every operand into bf16 hi + lo parts and accumulate
+//              hi*hi + lo*hi + hi*lo in float (the others run as PREC_F32)
+enum Prec { PREC_F64 = IDQ_F64, PREC_F32 = IDQ_F32, PREC_BF16 = IDQ_BF16, PREC_SPLIT = IDQ_BF16X3 };
+constexpr int kNumPrec = 4;
 
 // Activation buffers of the network hold a_l = sigma(h_l) (not h_l): the
 // SoftPlus is evaluated once, in the producing pass's epilogue, and the
@@ -56,11 +60,14 @@ struct ConvArgs {
   int gate_mask;        // run image i iff (1 << gate[i]) & gate_mask
   int img_div;          // solver image = net image / img_div
   unsigned long long* work_px;  // nullable: += output pixels actually computed
+  hipEvent_t ev0, ev1;  // nullable: timing events stamped by the launch itself
 };
 
 // Phase gate values written by the finalize kernel.
-enum Gate { G_DONE = 0, G_LOW = 1, G_FINAL = 2 };
-constexpr int GM_ACTIVE = (1 << G_LOW) | (1 << G_FINAL);
+//   G_LOW: bf16 phase, G_MID: split-bf16 phase, G_FINAL: the solve's own
+//   arithmetic (float32 after a bf16 start), which alone may stop an image.
+enum Gate { G_DONE = 0, G_LOW = 1, G_FINAL = 2, G_MID = 3 };
+constexpr int GM_ACTIVE = (1 << G_LOW) | (1 << G_FINAL) | (1 << G_MID);
 
 __device__ inline bool gate_open(const int* gate, int mask, int img) {
   return gate == nullptr || ((1 << gate[img]) & mask) != 0;
@@ -128,7 +135,7 @@ int launch_update(const UpdateArgs& a, int dtype, hipStream_t s);
 struct ImgState {
   int it, kr, status, done;
   int prec, it_low, stall, restarts;
-  int last_buf, pad0, pad1, pad2;
+  int last_buf, it_mid, pad1, pad2;
   double S, rel, best_rel, beta_eff;
 };
 struct FinalizeArgs {
@@ -139,6 +146,7 @@ struct FinalizeArgs {
   double* beta_eff;
   double beta, tol, restart_B2, switch_tol;
   int max_iter, fixed_iters, switch_patience;
+  int use_mid;          // the bf16 phase hands over to a split-bf16 phase first
   int buf_index;        // ping-pong buffer holding the new iterate
   double* history;      // nullable: [step][n] relative residuals
   int step;             // global update index of this finalize

@@ -16,7 +16,7 @@ import numpy as np
 __all__ = [
     "ground_truth", "noise_field", "make_batch", "he_normal_net",
     "gaussian_taps", "uniform_taps", "net_channels", "warmstart_channels",
-    "random_field",
+    "random_field", "warmstart_init",
 ]
 
 
@@ -130,3 +130,19 @@ def warmstart_channels():
     dec: 96->32->32->3. Returned as (c_in, c_out) per conv in execution order."""
     return [(3, 32), (32, 32), (32, 64), (64, 64), (64, 64), (64, 64),
             (96, 32), (32, 32), (32, 3)]
+
+
+def warmstart_init(seed: int = 0, out_scale: float = 0.1):
+    """Initial weights of the warm-start encoder-decoder: He-normal
+    W ~ N(0, 2 / (9 * C_in)) drawn layer by layer from ``default_rng(seed)``
+    in C order, the output layer scaled by ``out_scale`` (so that the initial
+    network output is small and x0 starts close to y), zero biases."""
+    rng = np.random.default_rng(seed)
+    chans = warmstart_channels()
+    out = []
+    for i, (cin, cout) in enumerate(chans):
+        W = rng.standard_normal((cout, cin, 3, 3)) * np.sqrt(2.0 / (9.0 * cin))
+        if i == len(chans) - 1:
+            W = W * out_scale
+        out.append((W, np.zeros(cout)))
+    return out

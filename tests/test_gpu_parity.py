@@ -59,6 +59,11 @@ def test_grad_reg_parity(name, c, shape, rng):
     assert np.max(np.abs(to_np(g32) - ref)) < 1e-4
     gbf = ctx.grad_reg(to_gpu(x, torch.float32), conv_prec="bf16")
     assert rel_err(to_np(gbf), ref) < 2e-2
+    # split bf16 (hi*hi + lo*hi + hi*lo): products good to ~2^-16, float32
+    # tolerance; the 64-channel passes run split, the image-facing ones float32
+    gx3 = ctx.grad_reg(to_gpu(x, torch.float32), conv_prec="bf16x3")
+    assert np.max(np.abs(to_np(gx3) - ref)) < 1e-4
+    assert rel_err(to_np(gx3), ref) < 1e-4
 
 
 def test_hvp_parity(rng):
@@ -173,6 +178,39 @@ def test_config2_bf16_then_f32_reaches_oracle_fixed_point():
     assert np.all(res32.status == 0)
     assert abs(int(res32.iters[0]) - int(info["iters"][0])) <= 10
     assert np.max(np.abs(to_np(x32) - x_or)) < 1e-4
+
+
+def test_config2_split_refinement_reaches_oracle_fixed_point():
+    """Errors against the oracle's fixed point (rel 1e-6) of solves stopped at
+    the metric's rel 1e-4: bf16 phase, split-bf16 phase, then float32 updates
+    (which alone stop an image) lands within the bf16 tolerance (2e-2) and
+    within a small factor of plain fp32 stopped at the same residual.  A split-only solve to rel 1e-5 (its floor is ~1.5e-6) shows the
+    bias of ~2^-17 products through this ill-conditioned problem (~1e-3 relative)."""
+    layers, taps, y, P = config2_small(1, 32, 32)
+    tau = 0.9 / S.power_iteration(P, y, y, synth.random_field(12345, y.shape), 30)
+    x_or, info = S.ideq_solve(P, y, y, 0.5, tau, tol=1e-6, max_iter=3000)
+    assert np.all(info["status"] == S.CONVERGED)
+    ctx = _ctx(layers, "blur", taps)
+    yg = to_gpu(y, torch.float32)
+    kw = dict(beta=0.5, tau=tau, lam=1.0, max_iter=3000)
+    x32, r32 = ctx.solve(yg, tol=1e-4, conv_prec="f32", **kw)
+    xbf, rbf = ctx.solve(yg, tol=1e-4, conv_prec="bf16", **kw)
+    xsr, rsr = ctx.solve(yg, tol=1e-4, conv_prec="bf16", refine_prec="bf16x3", **kw)
+    x3, r3 = ctx.solve(yg, tol=1e-5, conv_prec="bf16x3", **kw)
+    for r in (r32, rbf, rsr, r3):
+        assert np.all(r.status == 0)
+    assert np.all(rsr.iters_low > 0) and np.all(rsr.iters_mid > 0)
+    assert np.all(rsr.iters > rsr.iters_low + rsr.iters_mid)     # ended on fp32 updates
+    assert np.all(rbf.iters_mid == 0) and np.all(r32.iters_mid == 0)
+    e = {k: (rel_err(to_np(v), x_or), float(np.max(np.abs(to_np(v) - x_or))))
+         for k, v in (("f32@1e-4", x32), ("bf16+f32@1e-4", xbf), ("bf16+split@1e-4", xsr),
+                      ("split@1e-5", x3))}
+    print("errors vs oracle (rel, max-abs):", e, "iterations:",
+          r32.iters.tolist(), rbf.iters.tolist(), rsr.iters.tolist(), rsr.iters_low.tolist(),
+          rsr.iters_mid.tolist(), r3.iters.tolist())
+    assert e["bf16+split@1e-4"][0] < 2e-2
+    assert e["bf16+split@1e-4"][0] < max(3 * e["f32@1e-4"][0], 3 * e["bf16+f32@1e-4"][0])
+    assert e["split@1e-5"][0] < 5e-3
 
 
 def test_config3_tanh_blur_trajectory_f32():

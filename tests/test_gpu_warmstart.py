@@ -155,3 +155,79 @@ def test_solver_warm_start_equals_explicit_x0():
     xb, rb = ctx.solve(y, x0=x0, **kw)
     assert np.array_equal(ra.iters, rb.iters)
     assert np.array_equal(to_np(xa), to_np(xb))
+
+
+# ---- the trained network shipped with the package --------------------------------
+import os  # noqa: E402
+import time  # noqa: E402
+
+from gpu_util import rel_err  # noqa: E402
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2605_19705_amd", "weights", "warmstart_deblur.npy")
+
+
+def _trained():
+    assert os.path.exists(WEIGHTS), "trained warm-start weights missing from the package"
+    from paper_2605_19705_amd import WarmStart
+    return WarmStart(np.load(WEIGHTS).astype(np.float64), device=0)
+
+
+def _deblur(cfg_id, n, size):
+    from paper_2605_19705_amd import IDQ
+    from oracle import operators as O
+    layers = synth.he_normal_net(synth.net_channels("rgb64"), 0)
+    taps = synth.gaussian_taps(9, 1.6)
+    xt, nz = synth.make_batch(cfg_id, n, 3, size, size)
+    y = O.Operator("blur", taps).A(xt) + 0.01 * nz
+    return layers, taps, y, IDQ(layers, op_kind="blur", taps=taps, device=0)
+
+
+def test_trained_warm_start_reaches_the_oracle_fixed_point_from_y():
+    """A solve started from the trained warm start lands on the fixed point the
+    oracle reaches from x0 = y (held-out image, 1 x 3 x 48 x 48)."""
+    print("trained warm start vs oracle fixed point from y, 1x3x48x48", flush=True)
+    from oracle import operators as O, regularizer as R, solver as S
+    layers, taps, y, ctx = _deblur(5, 1, 48)
+    P = S.Problem(O.Operator("blur", taps), R.Net(layers), 1.0)
+    tau = 0.9 / S.power_iteration(P, y, y, synth.random_field(12345, y.shape), 30)
+    x_or, info = S.ideq_solve(P, y, y, 0.5, tau, tol=1e-6, max_iter=3000)
+    assert np.all(info["status"] == S.CONVERGED)
+    ws = _trained()
+    yg = to_gpu(y, torch.float32)
+    kw = dict(beta=0.5, tau=tau, lam=1.0, max_iter=3000, init="warmstart", ws=ws, ws_prec="bf16")
+    xbf, res = ctx.solve(yg, tol=1e-4, conv_prec="bf16", **kw)
+    assert np.all(res.status == 0)
+    assert rel_err(to_np(xbf), x_or) < 2e-2
+    x32, res32 = ctx.solve(yg, tol=1e-6, conv_prec="f32", **kw)
+    assert np.all(res32.status == 0)
+    assert np.max(np.abs(to_np(x32) - x_or)) < 1e-4
+
+
+def test_trained_warm_start_saves_iterations_at_512():
+    """Held-out batch of 4 x 3 x 512 x 512: the headline solve (bf16 phase + fp32
+    refinement to rel 1e-4) needs fewer iterations from the trained warm start than
+    from y or from zero, and ends at the same fixed point."""
+    print("trained warm start vs y / zero init, 4x3x512x512", flush=True)
+    layers, taps, y, ctx = _deblur(5, 4, 512)
+    yg = to_gpu(y, torch.float32)
+    v0 = to_gpu(synth.random_field(12345, y.shape), torch.float32)
+    tau = 0.9 / ctx.lipschitz(yg, yg, v0, lam=1.0, iters=30, conv_prec="f32")
+    ws = _trained()
+    kw = dict(beta=0.5, tau=tau, lam=1.0, tol=1e-4, max_iter=3000, conv_prec="bf16")
+    out = {}
+    for init in ("y", "zero", "warmstart"):
+        extra = dict(ws=ws, ws_prec="bf16") if init == "warmstart" else {}
+        ctx.solve(yg, init=init, **kw, **extra)        # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, res = ctx.solve(yg, init=init, **kw, **extra)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert np.all(res.status == 0), init
+        out[init] = (to_np(x), res, dt)
+        print(f"  init={init}: iterations {res.iters.tolist()} (bf16 {res.iters_low.tolist()}), "
+              f"{4 / dt:.1f} images/s", flush=True)
+    it = {k: float(np.mean(v[1].iters)) for k, v in out.items()}
+    assert it["warmstart"] < it["y"] and it["warmstart"] < it["zero"], it
+    assert rel_err(out["warmstart"][0], out["y"][0]) < 2e-2
