@@ -28,6 +28,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PROF_CLASSES = ["conv64_bf16", "conv64_f32", "conv_other", "stencil", "update", "warmstart",
+                "conv64_bf16x3"]
 METRIC = "restored 256^2 images/s at rel. residual 1e-4: BF16+warm-start vs FP32 plain"
 BF16_PEAK = 2.5e15     # MI355X dense bf16 matrix-core peak, FLOP/s
 F32_PEAK = 157.3e12    # MI355X dense fp32 matrix-core peak, FLOP/s
@@ -70,12 +72,14 @@ def make_problem(torch, n=8, h=256, w=256):
     return ctx, y.contiguous(), layers, taps, xt, nz
 
 
-def time_arm(torch, ctx, y, K, W, profile=False, **kw):
+def time_arm(torch, ctx, y, K, W, profile=None, **kw):
+    """W warm-up solves, then K timed solves; ``profile``: names of the kernel
+    classes whose launches are timed by HIP events inside the timed region."""
     for _ in range(W):
         ctx.solve(y, **kw)
     torch.cuda.synchronize()
     if profile:
-        ctx.profile(True)
+        ctx.profile(True, classes=profile)
     times, iters, low, mid = [], [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -94,6 +98,17 @@ def time_arm(torch, ctx, y, K, W, profile=False, **kw):
         ctx.profile(False)
     return dict(total_s=total, step_s=times, iters=iters, iters_low=low, iters_mid=mid, prof=prof,
                 x=x)
+
+
+def class_breakdown(torch, ctx, y, **kw):
+    """Device time per kernel class of one more solve (outside the timed region:
+    timing every class adds an event pair to each launch)."""
+    ctx.profile(True)
+    ctx.solve(y, **kw)
+    torch.cuda.synchronize()
+    p = ctx.profile_read()
+    ctx.profile(False)
+    return {k: {"ms": v[0], "launches": v[1]} for k, v in p.items()}
 
 
 def cpu_baseline(iters_per_image, sample_iters=3):
@@ -134,6 +149,8 @@ def main():
     ap.add_argument("--refine", default="bf16x3", choices=["f32", "bf16x3"],
                     help="bf16x3: a split-bf16 phase between the bf16 phase and the float32 "
                          "updates that end every solve; f32: straight to float32")
+    ap.add_argument("--profile-all", action="store_true",
+                    help="time every kernel class inside the timed region (slower)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB device-to-device (a plain copy "
                          "kernel of known size, for scaling hardware byte counters)")
@@ -182,7 +199,8 @@ def main():
 
     log(f"bench: headline arm (bf16 + fp32 refinement, init={init}), "
         f"{args.warmup} warmup + {args.steps} timed solves")
-    head = time_arm(torch, ctx, y, args.steps, args.warmup, profile=True, **head_kw)
+    head = time_arm(torch, ctx, y, args.steps, args.warmup,
+                    profile=PROF_CLASSES if args.profile_all else ["conv64_bf16"], **head_kw)
     n_img = y.shape[0]
     value = n_img * args.steps / head["total_s"]
     log(f"bench: headline {value:.2f} images/s, iterations {head['iters'][-1]}, "
@@ -191,8 +209,7 @@ def main():
     fp32 = None
     if not args.no_fp32:
         log("bench: fp32-plain arm")
-        fp32 = time_arm(torch, ctx, y, max(1, min(args.steps, 2)), 0, profile=False,
-                        conv_prec="f32", **common)
+        fp32 = time_arm(torch, ctx, y, max(1, min(args.steps, 2)), 0, conv_prec="f32", **common)
         fp32["value"] = n_img * len(fp32["step_s"]) / fp32["total_s"]
         log(f"bench: fp32 plain {fp32['value']:.2f} images/s, iterations {fp32['iters'][-1]}")
 
@@ -208,7 +225,7 @@ def main():
                 "kernel": "conv_mfma_kernel<bf16, 64, 64>", "launches": launches,
                 "avg_launch_us": avg_ms * 1e3,
                 "flop_per_launch": flops_per_launch}
-    phases = {k: {"ms": v[0], "launches": v[1]} for k, v in head["prof"].items()}
+    phases = class_breakdown(torch, ctx, y, **head_kw)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -246,7 +263,7 @@ def main():
             "ms_per_step": 1e3 * fp32["total_s"] / len(fp32["step_s"])},
         "speedup_vs_fp32_plain": None if fp32 is None else value / fp32["value"],
         "step_size": {"L": L, "tau": tau, "power_iteration_ms": t_L * 1e3},
-        "device_ms_by_class": phases,
+        "device_ms_by_class_one_solve": phases,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -235,7 +235,12 @@ int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_d
 #define IDQ_PROF_UPDATE        4   /* extrapolation, update, finalize            */
 #define IDQ_PROF_WARMSTART     5   /* warm-start network inference               */
 #define IDQ_PROF_CONV64_BF16X3 6   /* 64->64-channel conv passes, split-bf16 MFMA */
-/* Enable (on != 0) or disable accounting; resets all counters.  Synchronous. */
+/* Accounting of device time per class: on == 0 disables it; otherwise `on` is
+ * the bit mask of the classes to time (1 << IDQ_PROF_*; IDQ_PROF_ALL for all).
+ * Each timed launch costs its events (conv classes: stamped by the dispatch
+ * itself; the others: recorded around the launch).  Resets all counters.
+ * Synchronous. */
+#define IDQ_PROF_ALL 0x7fffffff
 int idq_profile_enable(idq_ctx* ctx, int on);
 /* Totals since the last enable: summed device time (ms), number of launches
  * and output pixels computed (conv classes; 0 otherwise).  Synchronous. */

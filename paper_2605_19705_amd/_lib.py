@@ -21,6 +21,7 @@ IDQ_INIT_Y, IDQ_INIT_ZERO, IDQ_INIT_WARMSTART = 0, 1, 2
 IDQ_MAX_LAYERS = 8
 IDQ_ST_CONVERGED, IDQ_ST_MAXITER, IDQ_ST_FIXED, IDQ_ST_NONFINITE = 0, 1, 2, -4
 IDQ_BWD_JFB, IDQ_BWD_IMPLICIT = 0, 1
+IDQ_PROF_ALL = 0x7fffffff
 PROF_CLASSES = {"conv64_bf16": 0, "conv64_f32": 1, "conv_other": 2, "stencil": 3, "update": 4,
                 "warmstart": 5, "conv64_bf16x3": 6}
 

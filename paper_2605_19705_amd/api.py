@@ -126,8 +126,13 @@ class IDQ:
                                        flat.size))
 
     # ---- device-time accounting ---------------------------------------------------
-    def profile(self, on=True):
-        L.check(L.lib().idq_profile_enable(self._h, int(bool(on))))
+    def profile(self, on=True, classes=None):
+        """Time device work per class; ``classes``: names of L.PROF_CLASSES to time
+        (all when None)."""
+        mask = 0
+        if on:
+            mask = L.IDQ_PROF_ALL if classes is None else sum(1 << L.PROF_CLASSES[c] for c in classes)
+        L.check(L.lib().idq_profile_enable(self._h, int(mask)))
 
     def profile_read(self):
         """{class: (total_ms, launches, pixels)} since the last profile(True)."""

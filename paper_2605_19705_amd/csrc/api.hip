@@ -111,6 +111,7 @@ int run_conv(idq_ctx* ctx, ConvArgs a, int prec, hipStream_t s) {
   if (a.CI == 64 && a.CO == 64 && prec != PREC_F64)
     cls = prec == PREC_BF16 ? PC_CONV_WIDE_BF16
                             : (prec == PREC_SPLIT ? PC_CONV_WIDE_SPLIT : PC_CONV_WIDE_F32);
+  if (!ctx->prof.timed(cls)) return launch_conv(a, prec, s);
   a.work_px = ctx->prof.dev_px + cls;
   // the launcher stamps the events from the dispatch itself (hipExtLaunchKernel)
   // so that they time the kernel alone, not its launch latency
@@ -125,7 +126,7 @@ int run_conv(idq_ctx* ctx, ConvArgs a, int prec, hipStream_t s) {
 
 template <class F>
 int profiled(idq_ctx* ctx, int cls, hipStream_t s, F&& f) {
-  if (!ctx->prof.on) return f();
+  if (!ctx->prof.timed(cls)) return f();
   ProfRec r;
   IDQ_TRY(ctx->prof.begin(cls, s, &r));
   IDQ_TRY(f());
@@ -1022,6 +1023,7 @@ int idq_profile_enable(idq_ctx* ctx, int on) {
       ctx->prof.launches[i] = 0;
     }
     ctx->prof.on = on != 0;
+    ctx->prof.mask = static_cast<unsigned>(on);
     return IDQ_OK;
   });
 }

@@ -48,6 +48,8 @@ struct ProfRec {
 };
 struct Profiler {
   bool on = false;
+  unsigned mask = 0;   // classes timed while on (bit cls)
+  bool timed(int cls) const { return on && ((mask >> cls) & 1u); }
   std::vector<hipEvent_t> pool;
   std::vector<ProfRec> pending;
   double ms[PC_COUNT] = {};

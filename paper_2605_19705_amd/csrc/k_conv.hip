@@ -117,6 +117,8 @@ int launch_conv_mfma(const ConvArgs& a, int prec, hipStream_t s);  // k_conv_mfm
 // E_DELTA / E_RAW / E_DDOT (float32) or NCHW outputs (CO <= 4) through E_RES /
 // E_SUB; the float32 tangent prologue feeds E_RAW (wide) or E_SUB (thin).
 static bool mfma_form_ok(const ConvArgs& a, int prec) {
+  // the bf16 kernels evaluate SoftPlus (and its derivative) only
+  if (prec == PREC_BF16 && a.act != IDQ_ACT_SOFTPLUS) return false;
   const bool in_ok = a.CI <= 4 ? (a.in_fmt == F_NCHW && a.pro == P_NONE)
                                : (a.in_fmt == F_NHWC && (a.pro == P_NONE || prec == PREC_F32));
   bool out_ok;

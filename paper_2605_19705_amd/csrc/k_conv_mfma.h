@@ -223,11 +223,179 @@ __device__ inline void mma(f32x4_t& acc, const u32x4_t& af, const u32x4_t& bf) {
   }
 }
 
+// Output of one (row r, channel block j) piece of a tile: the lane's 4 output
+// channels 16 j + 4 g .. + 3 at pixel (ty0 + 4 wv + r, tx0 + c16).
+template <class C, int CO, int EPI>
+__device__ inline void epilogue_piece(const ConvArgs& a, const f32x4_t& accv,
+                                      const u32x4_t& e0pre, const float (&bias4)[4], int ni,
+                                      int ty0, int tx0, int wv, int r, int j, int g, int c16,
+                                      bool sp) {
+  const int oy = ty0 + wv * RW + r, ox = tx0 + c16;
+  if (oy >= a.H || ox >= a.W) return;
+  const int co0 = 16 * j + 4 * g;
+  if (co0 >= CO) return;
+  constexpr bool pre_e0 = EPI == E_DELTA && CO % 4 == 0;
+  if constexpr (EPI != E_RES && EPI != E_SUB && EPI != E_ADD) {
+    const size_t o = ((static_cast<size_t>(ni) * a.H + oy) * a.W + ox) * CO + co0;
+    float v[4], w1[4];
+    f32x4_t dd0 = {0.f, 0.f, 0.f, 0.f}, dd1 = dd0, dd2 = dd0;
+    bool two = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = co0 + i;
+      const float x = accv[i];
+      float res = x;
+      w1[i] = 0.f;
+      if (co < CO) {
+        if constexpr (EPI == E_ACT) {
+          const float hv = x + bias4[i];
+          res = sp ? (C::BF ? softplus_fast(hv) : softplus_f(hv)) : hv;
+        } else if constexpr (EPI == E_DELTA) {
+          float av;
+          if (pre_e0) {
+            if (C::BF) {
+              bf16 hb;
+              hb.u = static_cast<uint16_t>(e0pre[i >> 1] >> ((i & 1) * 16));
+              av = bf2f(hb);
+            } else {
+              av = u2f(e0pre[i]);
+            }
+          } else {
+            av = C::BF ? bf2f(static_cast<const bf16*>(a.e0)[o + i])
+                       : static_cast<const float*>(a.e0)[o + i];
+          }
+          res = (sp ? (C::BF ? dsp_from_a_fast(av) : dsp_from_a(av)) : 1.f) * x;
+        } else if constexpr (EPI == E_DDOT) {
+          // float32 passes only (the HVP is not run in bf16)
+          if (CO % 4 == 0 && i == 0) {
+            dd0 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e0) + o);
+            dd1 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e1) + o);
+            dd2 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e2) + o);
+          }
+          const float av = CO % 4 == 0 ? dd0[i] : static_cast<const float*>(a.e0)[o + i];
+          const float hd = CO % 4 == 0 ? dd1[i] : static_cast<const float*>(a.e1)[o + i];
+          const float tv = CO % 4 == 0 ? dd2[i] : static_cast<const float*>(a.e2)[o + i];
+          const float s1 = sp ? dsp_from_a(av) : 1.f;
+          const float s2 = sp ? s1 * (1.f - s1) : 0.f;
+          res = s2 * hd * tv + s1 * x;
+          w1[i] = s1 * tv;
+          two = true;
+        }
+      }
+      v[i] = res;
+    }
+    if (C::BF) {
+      bf16* out = static_cast<bf16*>(a.out0) + o;
+      if (CO % 4 == 0) {
+        uint2 pk;
+        pk.x = pk_bf16(v[0], v[1]);
+        pk.y = pk_bf16(v[2], v[3]);
+        *reinterpret_cast<uint2*>(out) = pk;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (co0 + i < CO) out[i] = f2bf(v[i]);
+      }
+    } else {
+      float* out = static_cast<float*>(a.out0) + o;
+      if (CO % 4 == 0) {
+        *reinterpret_cast<f32x4_t*>(out) = f32x4_t{v[0], v[1], v[2], v[3]};
+        if (two)
+          *reinterpret_cast<f32x4_t*>(static_cast<float*>(a.out1) + o) =
+              f32x4_t{w1[0], w1[1], w1[2], w1[3]};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (co0 + i < CO) {
+            out[i] = v[i];
+            if (two) static_cast<float*>(a.out1)[o + i] = w1[i];
+          }
+      }
+    }
+  } else {
+    // state tensor output in NCHW (float)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = co0 + i;
+      if (co >= CO) break;
+      const size_t o = ((static_cast<size_t>(ni) * CO + co) * a.H + oy) * a.W + ox;
+      const float x = accv[i];
+      const float* e0 = static_cast<const float*>(a.e0);
+      float res;
+      if constexpr (EPI == E_RES)
+        res = e0[o] - (x + bias4[i]);
+      else if constexpr (EPI == E_ADD)
+        res = e0[o] + (x + bias4[i]);
+      else
+        res = e0[o] - x;
+      static_cast<float*>(a.out0)[o] = res;
+    }
+  }
+}
+
+// Buffer resource over `bytes` bytes at `base` (raw addressing, gfx9 word 3);
+// a store whose offset is at or beyond `bytes` is dropped by the hardware.
+__device__ inline __amdgpu_buffer_rsrc_t out_rsrc(void* base, unsigned bytes) {
+  // the arguments are workgroup-uniform; say so, or the compiler wraps every
+  // store in a loop over the distinct resources of the wave
+  const uint64_t p = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(p));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(p >> 32));
+  const uint32_t n = __builtin_amdgcn_readfirstlane(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo), static_cast<short>(0),
+      static_cast<int>(n), 0x00020000);
+}
+constexpr unsigned kDropOffset = 0x80000000u;  // beyond every resource we build
+
+typedef __attribute__((ext_vector_type(2))) unsigned u32x2_v;
+
+// Branch-free output piece of the pipelined bf16 kernels (NHWC bf16 output,
+// CO a multiple of 16): lanes outside the image store to kDropOffset, and a
+// resource of zero bytes (no previous tile yet) drops every store, so the
+// piece is one straight run of VALU work that can sit between the MFMAs.
+template <class C, int CO, int EPI>
+__device__ inline void epilogue_piece_pipe(const ConvArgs& a, __amdgpu_buffer_rsrc_t rs,
+                                           const f32x4_t& accv, const u32x4_t& e0pre,
+                                           const float (&bias4)[4], int ty0, int tx0, int wv,
+                                           int r, int j, int g, int c16, bool sp) {
+  static_assert(C::BF && CO % 16 == 0, "pipelined pieces store bf16 NHWC rows");
+  (void)sp;  // SoftPlus only: bf16 passes of other activations take the direct kernel
+  const int ly = wv * RW + r, oy = ty0 + ly, ox = tx0 + c16;
+  const int co0 = 16 * j + 4 * g;
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float x = accv[i];
+    if constexpr (EPI == E_ACT) {
+      const float hv = x + bias4[i];
+      v[i] = softplus_fast(hv);
+    } else if constexpr (EPI == E_DELTA) {
+      const float av = u2f((e0pre[i >> 1] << ((i & 1) ? 0 : 16)) & 0xffff0000u);
+      v[i] = dsp_from_a_fast(av) * x;
+    } else {
+      v[i] = x;
+    }
+  }
+  const u32x2_v pk = {pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])};
+  const bool ok = oy < a.H && ox < a.W;
+  const unsigned off = ok ? (static_cast<unsigned>(ly * a.W + ox) * CO + co0) * 2u : kDropOffset;
+  __builtin_amdgcn_raw_buffer_store_b64(pk, rs, static_cast<int>(off), 0, 0);
+}
+
 template <int PREC, int CI, int CO, int PRO, int EPI>
 __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int ntx, int nty,
                                                                int ntiles) {
   using C = Cfg<PREC, CI, CO>;
   static_assert(!C::SPLIT || PRO == P_NONE, "split passes take plain operands");
+  // bf16 row-reuse kernels run software-pipelined: the epilogue of the previous
+  // tile is issued in pieces between the matrix-core groups of the current one,
+  // so its VALU work (SoftPlus / sigma', packing, stores) executes while the
+  // MFMAs are in flight instead of after them
+  constexpr bool PIPE = C::ROWS && C::BF && CO % 16 == 0 &&
+                        (EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW);
+  constexpr int NPIECE = RW * C::NJ;
+  constexpr bool pre_e0 = EPI == E_DELTA && CO % 4 == 0;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   char* lin = smem;
   const u32x4_t* lw = reinterpret_cast<const u32x4_t*>(smem + C::LDS_IN);
@@ -236,7 +404,9 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, c16 = lane & 15;
   const bool sp = a.act == IDQ_ACT_SOFTPLUS;
   const int tiles_per_img = ntx * nty;
-  auto open = [&](int t) { return gate_open(a.gate, a.gate_mask, (t / tiles_per_img) / a.img_div); };
+  auto open = [&](int t) {
+    return gate_open_uniform(a.gate, a.gate_mask, (t / tiles_per_img) / a.img_div);
+  };
 
   // first open tile of this workgroup (uniform across it); a workgroup with
   // none leaves before staging weights, so a pass whose images are all in
@@ -245,9 +415,32 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
   while (t < ntiles && !open(t)) t += gridDim.x;
   if (t >= ntiles) return;
 
+  // the first tile's halo is requested before the weights, and the weight
+  // fragments are fetched in batches of WB loads per thread before any is
+  // written to LDS, so the L2 round trips of the prologue overlap
+  Prefetch<C, PRO> pf;
+  {
+    const int ni = t / tiles_per_img, rem = t - ni * tiles_per_img;
+    load_tile<C, CI, PRO>(a, pf, ni, (rem / ntx) * TH, (rem % ntx) * TW, tid);
+  }
   if (C::WLDS) {
+    constexpr int NW = C::NCH * C::NJ * 64;          // 16-byte fragments
+    constexpr int PER = (NW + kThreads - 1) / kThreads;
+    constexpr int WB = PER < 24 ? PER : 24;
     u32x4_t* dst = reinterpret_cast<u32x4_t*>(smem + C::LDS_IN);
-    for (int i = tid; i < C::NCH * C::NJ * 64; i += kThreads) dst[i] = gw[i];
+    for (int b0 = 0; b0 < PER; b0 += WB) {
+      u32x4_t wbuf[WB];
+#pragma unroll
+      for (int q = 0; q < WB; ++q) {
+        const int i = tid + (b0 + q) * kThreads;
+        if (i < NW) wbuf[q] = gw[i];
+      }
+#pragma unroll
+      for (int q = 0; q < WB; ++q) {
+        const int i = tid + (b0 + q) * kThreads;
+        if (i < NW) dst[i] = wbuf[q];
+      }
+    }
   }
 
   // bias of the 16 output channels this lane owns in the epilogue
@@ -263,11 +456,22 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       }
   }
 
-  Prefetch<C, PRO> pf;
-  {
-    const int ni = t / tiles_per_img, rem = t - ni * tiles_per_img;
-    load_tile<C, CI, PRO>(a, pf, ni, (rem / ntx) * TH, (rem % ntx) * TW, tid);
-  }
+  // the previous tile (PIPE): accumulators, epilogue operand, position and
+  // the output resource over its rows (none before the first tile)
+  f32x4_t accp[PIPE ? RW : 1][PIPE ? C::NJ : 1];
+  EpiPrefetch<C> epp;
+  int pty0 = 0, ptx0 = 0;
+  __amdgpu_buffer_rsrc_t prs = out_rsrc(a.out0, 0u);
+  auto piece_prev = [&](int k) {
+    if constexpr (PIPE) {
+      if (k < NPIECE) {
+        const int r = k / C::NJ, j = k % C::NJ;
+        epilogue_piece_pipe<C, CO, EPI>(a, prs, accp[r][j], epp.v[r][j], bias_r[j], pty0, ptx0,
+                                        wv, r, j, g, c16, sp);
+      }
+    }
+  };
+
   while (t < ntiles) {
     const int ni = t / tiles_per_img;
     const int rem = t - ni * tiles_per_img;
@@ -288,7 +492,6 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
     // the epilogue's sigma(h) operand of this tile, fetched now so that its
     // latency hides behind the matrix-core work
     EpiPrefetch<C> ep;
-    constexpr bool pre_e0 = EPI == E_DELTA && CO % 4 == 0;
     if (pre_e0) {
 #pragma unroll
       for (int r = 0; r < RW; ++r) {
@@ -363,6 +566,7 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
               }
               mma<C>(acc[r][j], afc[j], brow[r + dy]);
             }
+          piece_prev(dxc * 3 + dy);
 #pragma unroll
           for (int j = 0; j < C::NJ; ++j) afc[j] = afn[j];
           if (C::SPLIT) {
@@ -420,113 +624,38 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       }
     }
     // ---- epilogue ----------------------------------------------------------------
+    if constexpr (PIPE) {
+      // pieces of the previous tile that found no matrix-core group to hide in
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const int oy = ty0 + wv * RW + r, ox = tx0 + c16;
-      if (oy >= a.H || ox >= a.W) continue;
+      for (int k = 9 * C::CPT; k < NPIECE; ++k) piece_prev(k);
 #pragma unroll
-      for (int j = 0; j < C::NJ; ++j) {
-        const int co0 = 16 * j + 4 * g;
-        if (co0 >= CO) continue;
-        if constexpr (EPI != E_RES && EPI != E_SUB && EPI != E_ADD) {
-          const size_t o = ((static_cast<size_t>(ni) * a.H + oy) * a.W + ox) * CO + co0;
-          float v[4], w1[4];
-          f32x4_t dd0 = {0.f, 0.f, 0.f, 0.f}, dd1 = dd0, dd2 = dd0;
-          bool two = false;
+      for (int r = 0; r < RW; ++r)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int co = co0 + i;
-            const float x = acc[r][j][i];
-            float res = x;
-            w1[i] = 0.f;
-            if (co < CO) {
-              if constexpr (EPI == E_ACT) {
-                  const float hv = x + bias_r[j][i];
-                  res = sp ? (C::BF ? softplus_fast(hv) : softplus_f(hv)) : hv;
-              } else if constexpr (EPI == E_DELTA) {
-                  float av;
-                  if (pre_e0) {
-                    if (C::BF) {
-                      bf16 hb;
-                      hb.u = static_cast<uint16_t>(ep.v[r][j][i >> 1] >> ((i & 1) * 16));
-                      av = bf2f(hb);
-                    } else {
-                      av = u2f(ep.v[r][j][i]);
-                    }
-                  } else {
-                    av = C::BF ? bf2f(static_cast<const bf16*>(a.e0)[o + i])
-                               : static_cast<const float*>(a.e0)[o + i];
-                  }
-                  res = (sp ? (C::BF ? dsp_from_a_fast(av) : dsp_from_a(av)) : 1.f) * x;
-              } else if constexpr (EPI == E_DDOT) {
-                  // float32 passes only (the HVP is not run in bf16)
-                  if (CO % 4 == 0 && i == 0) {
-                    dd0 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e0) + o);
-                    dd1 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e1) + o);
-                    dd2 = *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(a.e2) + o);
-                  }
-                  const float av = CO % 4 == 0 ? dd0[i] : static_cast<const float*>(a.e0)[o + i];
-                  const float hd = CO % 4 == 0 ? dd1[i] : static_cast<const float*>(a.e1)[o + i];
-                  const float tv = CO % 4 == 0 ? dd2[i] : static_cast<const float*>(a.e2)[o + i];
-                  const float s1 = sp ? dsp_from_a(av) : 1.f;
-                  const float s2 = sp ? s1 * (1.f - s1) : 0.f;
-                  res = s2 * hd * tv + s1 * x;
-                  w1[i] = s1 * tv;
-                  two = true;
-              }
-            }
-            v[i] = res;
-          }
-          if (C::BF) {
-            bf16* out = static_cast<bf16*>(a.out0) + o;
-            if (CO % 4 == 0) {
-              uint2 pk;
-              pk.x = pk_bf16(v[0], v[1]);
-              pk.y = pk_bf16(v[2], v[3]);
-              *reinterpret_cast<uint2*>(out) = pk;
-            } else {
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                if (co0 + i < CO) out[i] = f2bf(v[i]);
-            }
-          } else {
-            float* out = static_cast<float*>(a.out0) + o;
-            if (CO % 4 == 0) {
-              *reinterpret_cast<f32x4_t*>(out) = f32x4_t{v[0], v[1], v[2], v[3]};
-              if (two)
-                *reinterpret_cast<f32x4_t*>(static_cast<float*>(a.out1) + o) =
-                    f32x4_t{w1[0], w1[1], w1[2], w1[3]};
-            } else {
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                if (co0 + i < CO) {
-                  out[i] = v[i];
-                  if (two) static_cast<float*>(a.out1)[o + i] = w1[i];
-                }
-            }
-          }
-        } else {
-          // state tensor output in NCHW (float)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int co = co0 + i;
-            if (co >= CO) break;
-            const size_t o = ((static_cast<size_t>(ni) * CO + co) * a.H + oy) * a.W + ox;
-            const float x = acc[r][j][i];
-            const float* e0 = static_cast<const float*>(a.e0);
-            float res;
-            if constexpr (EPI == E_RES)
-              res = e0[o] - (x + bias_r[j][i]);
-            else if constexpr (EPI == E_ADD)
-              res = e0[o] + (x + bias_r[j][i]);
-            else
-              res = e0[o] - x;
-            static_cast<float*>(a.out0)[o] = res;
-          }
+        for (int j = 0; j < C::NJ; ++j) {
+          accp[r][j] = acc[r][j];
+          epp.v[r][j] = ep.v[r][j];
         }
+      pty0 = ty0;
+      ptx0 = tx0;
+      {
+        const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
+        const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
+        prs = out_rsrc(static_cast<bf16*>(a.out0) + row0,
+                       static_cast<unsigned>(rows) * a.W * CO * 2u);
       }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int j = 0; j < C::NJ; ++j)
+          epilogue_piece<C, CO, EPI>(a, acc[r][j], ep.v[r][j], bias_r[j], ni, ty0, tx0, wv, r, j,
+                                     g, c16, sp);
     }
     t = tn;
+  }
+  if constexpr (PIPE) {
+#pragma unroll
+    for (int k = 0; k < NPIECE; ++k) piece_prev(k);
   }
 }
 
@@ -551,6 +680,10 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
     attr_set = true;
   }
   const int ntx = (a.W + TW - 1) / TW, nty = (a.H + TH - 1) / TH;
+  // the pipelined epilogue addresses one tile's rows through a buffer resource
+  // whose byte count must stay below the drop offset
+  if (static_cast<long long>(TH) * a.W * CO * 4 >= static_cast<long long>(kDropOffset))
+    return fail(IDQ_E_UNSUPPORTED, "image too wide for the MFMA conv");
   const long long nt = static_cast<long long>(a.NI) * ntx * nty;
   if (nt > 0x7fffffff) return fail(IDQ_E_INVAL, "too many tiles");
   const int ntiles = static_cast<int>(nt);

@@ -72,6 +72,15 @@ constexpr int GM_ACTIVE = (1 << G_LOW) | (1 << G_FINAL) | (1 << G_MID);
 __device__ inline bool gate_open(const int* gate, int mask, int img) {
   return gate == nullptr || ((1 << gate[img]) & mask) != 0;
 }
+// The same test for a workgroup-uniform image index, read through the scalar
+// unit (the gate array is not written while a conv pass runs): a vector load
+// here would make the wave wait for all of its outstanding stores as well.
+__device__ inline bool gate_open_uniform(const int* gate, int mask, int img) {
+  if (gate == nullptr) return true;
+  typedef const __attribute__((address_space(4))) int* const_ptr;
+  const const_ptr cg = (const_ptr)(gate);  // address-space cast: constant memory
+  return ((1 << cg[img]) & mask) != 0;
+}
 
 int launch_conv(const ConvArgs& a, int prec, hipStream_t s);
 
