@@ -39,10 +39,10 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # profiles/conv_bf16_64x64_deblur_8x3x256_hbm_counters.md (FETCH x 2.0, WRITE x 1.0,
 # the factors a 256 MiB device copy gives); valid only while the kernel's device
 # code is the one measured (sha256 of its two sources below), else reported as null.
-TRAFFIC_BYTES_PER_LAUNCH = 121805 * 1024
+TRAFFIC_BYTES_PER_LAUNCH = 123247461
 TRAFFIC_SOURCES = ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                    "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")
-TRAFFIC_SHA256 = "4241daf86a97debd65c342a4d9b80d7154e16d8a45ed48bd9c78cee94e760f94"
+TRAFFIC_SHA256 = "1b920598a8d757a8c4436599800bafd3c537c23d674c5b5deb56ddbff6476a51"
 
 
 def sources_sha256():
@@ -222,6 +222,9 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / BF16_PEAK,
                 "traffic": TRAFFIC_BYTES_PER_LAUNCH if sources_sha256() == TRAFFIC_SHA256 else None,
                 "traffic_unit": "bytes per launch",
+                # E_ACT passes move 128 B in + 128 B out per pixel, E_DELTA 256 + 128;
+                # the solve runs them in equal numbers
+                "algorithmic_bytes": 320.0 * px / max(launches, 1),
                 "kernel": "conv_mfma_kernel<bf16, 64, 64>", "launches": launches,
                 "avg_launch_us": avg_ms * 1e3,
                 "flop_per_launch": flops_per_launch}
