@@ -73,6 +73,13 @@ __device__ inline double dsp_from_a(double a) { return -expm1(-a); }
 __device__ inline float exp_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 __device__ inline float log_fast(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 __device__ inline float dsp_from_a_fast(float a) { return 1.f - exp_fast(-a); }
+// float32 conv epilogues: the hardware exp2 / log2 (about 1 ulp each) without
+// the library's range reduction; absolute error of a few 1e-8 on values of
+// order one (for t << 0 softplus is e^t, below that error).
+__device__ inline float softplus_hw(float t) {
+  return fmaxf(t, 0.f) + log_fast(1.f + exp_fast(-fabsf(t)));
+}
+__device__ inline float dsp_from_a_hw(float a) { return 1.f - exp_fast(-a); }
 // softplus(t) = max(t, 0) + log1p(u), u = exp(-|t|) in (0, 1], with log1p(u) =
 // u P(u), P the degree-4 least-squares fit of log1p(u)/u on Chebyshev nodes of
 // [0, 1] (relative error below 6e-5, far under the 2^-9 of bf16 storage): one

@@ -249,7 +249,7 @@ __device__ inline void epilogue_piece(const ConvArgs& a, const f32x4_t& accv,
       if (co < CO) {
         if constexpr (EPI == E_ACT) {
           const float hv = x + bias4[i];
-          res = sp ? (C::BF ? softplus_fast(hv) : softplus_f(hv)) : hv;
+          res = sp ? (C::BF ? softplus_fast(hv) : softplus_hw(hv)) : hv;
         } else if constexpr (EPI == E_DELTA) {
           float av;
           if (pre_e0) {
@@ -264,7 +264,7 @@ __device__ inline void epilogue_piece(const ConvArgs& a, const f32x4_t& accv,
             av = C::BF ? bf2f(static_cast<const bf16*>(a.e0)[o + i])
                        : static_cast<const float*>(a.e0)[o + i];
           }
-          res = (sp ? (C::BF ? dsp_from_a_fast(av) : dsp_from_a(av)) : 1.f) * x;
+          res = (sp ? (C::BF ? dsp_from_a_fast(av) : dsp_from_a_hw(av)) : 1.f) * x;
         } else if constexpr (EPI == E_DDOT) {
           // float32 passes only (the HVP is not run in bf16)
           if (CO % 4 == 0 && i == 0) {

@@ -112,6 +112,106 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, Taps<T> 
   }
 }
 
+// Output transform of a stencil mode for one pixel (s0 = k (*) in0, s1 = k (*) in1).
+template <typename T, int MODE>
+__device__ inline T stencil_out(T s0, T s1, T aux, T g, T tg) {
+  const T c1 = g / tg;
+  switch (MODE) {
+    case S_B:
+    case S_BT: return s0;
+    case S_B_MINUS: return s0 - aux;
+    case S_TANH_A: return tanh(g * s0) / tg;
+    case S_TANH_WRES: {
+      const T t = tanh(g * s0);
+      return c1 * (T(1) - t * t) * (t / tg - aux);
+    }
+    case S_TANH_JTW: {
+      const T t = tanh(g * s0);
+      return c1 * (T(1) - t * t) * aux;
+    }
+    default: {  // S_TANH_HESS
+      const T t = tanh(g * s0);
+      const T sech2 = T(1) - t * t;
+      const T curv = T(-2) * g * g / tg * t * sech2;
+      return s1 * (c1 * c1 * sech2 * sech2 + (t / tg - aux) * curv);
+    }
+  }
+}
+
+// Square K x K taps (K odd, compile time): 16 x 32 output tiles, two
+// horizontally adjacent outputs per thread sharing their K + 1 row reads, all
+// tap loops unrolled (the taps then sit in scalar registers).
+constexpr int kSTY = 16, kSTX = 32;
+template <typename T, int MODE, int K>
+__global__ __launch_bounds__(kBlock) void stencil_k_kernel(StencilArgs a, Taps<T> taps) {
+  constexpr int R = (K - 1) / 2, LH = kSTY + K - 1, LW = kSTX + K - 1;
+  constexpr bool TWO = MODE == S_TANH_HESS;
+  __shared__ T tile0[LH * LW];
+  __shared__ T tile1[TWO ? LH * LW : 1];
+  const int plane = blockIdx.z;
+  if (a.gate && a.gate[plane / a.plane_div] == G_DONE) return;
+  const int ty0 = blockIdx.y * kSTY, tx0 = blockIdx.x * kSTX;
+  const size_t pbase = static_cast<size_t>(plane) * a.H * a.W;
+  const T* in0 = static_cast<const T*>(a.in0) + pbase;
+  const T* in1 = static_cast<const T*>(a.in1) + (TWO ? pbase : 0);
+  for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+    const int ly = i / LW, lx = i - (i / LW) * LW;
+    const int gy = wrap(ty0 - R + ly, a.H), gx = wrap(tx0 - R + lx, a.W);
+    const size_t src = static_cast<size_t>(gy) * a.W + gx;
+    tile0[i] = in0[src];
+    if (TWO) tile1[i] = in1[src];
+  }
+  __syncthreads();
+  const int ly = threadIdx.x / (kSTX / 2), lx = (threadIdx.x % (kSTX / 2)) * 2;
+  const int oy = ty0 + ly, ox = tx0 + lx;
+  if (oy >= a.H || ox >= a.W) return;
+  T s0a = T(0), s0b = T(0), s1a = T(0), s1b = T(0);
+#pragma unroll
+  for (int p = 0; p < K; ++p) {
+    T r0[K + 1], r1[TWO ? K + 1 : 1];
+#pragma unroll
+    for (int q = 0; q <= K; ++q) {
+      r0[q] = tile0[(ly + p) * LW + lx + q];
+      if (TWO) r1[q] = tile1[(ly + p) * LW + lx + q];
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const T kv = taps.k[p * K + q];
+      s0a += kv * r0[q];
+      s0b += kv * r0[q + 1];
+      if (TWO) {
+        s1a += kv * r1[q];
+        s1b += kv * r1[q + 1];
+      }
+    }
+  }
+  const T g = static_cast<T>(a.gain), tg = tanh(g);
+  const T* aux = static_cast<const T*>(a.aux);
+  T* out = static_cast<T*>(a.out);
+  const size_t o = pbase + static_cast<size_t>(oy) * a.W + ox;
+  const bool uses_aux = MODE == S_B_MINUS || MODE == S_TANH_WRES || MODE == S_TANH_JTW ||
+                        MODE == S_TANH_HESS;
+  out[o] = stencil_out<T, MODE>(s0a, s1a, uses_aux ? aux[o] : T(0), g, tg);
+  if (ox + 1 < a.W) out[o + 1] = stencil_out<T, MODE>(s0b, s1b, uses_aux ? aux[o + 1] : T(0), g, tg);
+}
+
+template <typename T, int K>
+int stencil_k_launch(const StencilArgs& a, const Taps<T>& tp, hipStream_t s) {
+  dim3 grid((a.W + kSTX - 1) / kSTX, (a.H + kSTY - 1) / kSTY, a.NP);
+  switch (a.mode) {
+    case S_B: stencil_k_kernel<T, S_B, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_BT: stencil_k_kernel<T, S_BT, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_B_MINUS: stencil_k_kernel<T, S_B_MINUS, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_A: stencil_k_kernel<T, S_TANH_A, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_WRES: stencil_k_kernel<T, S_TANH_WRES, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_JTW: stencil_k_kernel<T, S_TANH_JTW, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_HESS: stencil_k_kernel<T, S_TANH_HESS, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    default: return fail(IDQ_E_INVAL, "bad stencil mode");
+  }
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
 template <typename T>
 int stencil_dispatch(const StencilArgs& a, const double* taps_host, hipStream_t s) {
   Taps<T> tp;
@@ -121,6 +221,10 @@ int stencil_dispatch(const StencilArgs& a, const double* taps_host, hipStream_t 
       const int sp = flip ? a.kh - 1 - p : p, sq = flip ? a.kw - 1 - q : q;
       tp.k[p * a.kw + q] = static_cast<T>(taps_host[sp * a.kw + sq]);
     }
+  if (a.kh == a.kw && a.kh == 9) return stencil_k_launch<T, 9>(a, tp, s);
+  if (a.kh == a.kw && a.kh == 7) return stencil_k_launch<T, 7>(a, tp, s);
+  if (a.kh == a.kw && a.kh == 5) return stencil_k_launch<T, 5>(a, tp, s);
+  if (a.kh == a.kw && a.kh == 3) return stencil_k_launch<T, 3>(a, tp, s);
   dim3 grid((a.W + kTile - 1) / kTile, (a.H + kTile - 1) / kTile, a.NP);
   switch (a.mode) {
     case S_B: stencil_kernel<T, S_B><<<grid, kBlock, 0, s>>>(a, tp); break;
