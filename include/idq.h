@@ -114,8 +114,10 @@ typedef struct {
     int    grad_at;         /* IDQ_GRAD_AT_*                                     */
     int    conv_prec;       /* IDQ_F64 (dtype F64 only) | IDQ_F32 | IDQ_BF16 |
                                IDQ_BF16X3                                         */
-    double switch_tol;      /* BF16 phase ends when rel < switch_tol ...          */
-    int    switch_patience; /* ... or after this many BF16 steps with no new best */
+    double switch_tol;      /* BF16 phase ends when rel < switch_tol (default
+                               2e-3) ...                                          */
+    int    switch_patience; /* ... or after this many BF16 steps with no new best
+                               (default 5)                                        */
     int    power_iters;     /* power iterations when tau == 0                    */
     const void* power_v0;   /* device, shape of y: power-iteration start vector  */
     int    poll_every;      /* iterations enqueued between host polls            */

@@ -190,7 +190,7 @@ class IDQ:
     # ---- solver ------------------------------------------------------------------
     def solve(self, y, x0=None, out=None, beta=0.5, tau=0.0, lam=1.0, tol=1e-4, max_iter=1000,
               fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
-              switch_tol=1e-3, switch_patience=10, power_iters=30, power_v0=None,
+              switch_tol=2e-3, switch_patience=5, power_iters=30, power_v0=None,
               poll_every=8, init="y", ws=None, ws_prec="bf16", refine_prec="f32",
               history=0):
         o = L.SolveOpts()

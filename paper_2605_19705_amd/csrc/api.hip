@@ -931,8 +931,8 @@ void idq_solve_opts_default(idq_solve_opts* o) {
   o->restart_B = 0.0;
   o->grad_at = IDQ_GRAD_AT_EXTRAPOLATED;
   o->conv_prec = IDQ_F32;
-  o->switch_tol = 1e-3;
-  o->switch_patience = 10;
+  o->switch_tol = 2e-3;
+  o->switch_patience = 5;
   o->power_iters = 30;
   o->poll_every = 8;
   o->init = IDQ_INIT_Y;

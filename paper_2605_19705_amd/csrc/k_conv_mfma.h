@@ -354,13 +354,15 @@ typedef __attribute__((ext_vector_type(2))) unsigned u32x2_v;
 // CO a multiple of 16): lanes outside the image store to kDropOffset, and a
 // resource of zero bytes (no previous tile yet) drops every store, so the
 // piece is one straight run of VALU work that can sit between the MFMAs.
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4_v;
+
 template <class C, int CO, int EPI>
 __device__ inline void epilogue_piece_pipe(const ConvArgs& a, __amdgpu_buffer_rsrc_t rs,
                                            const f32x4_t& accv, const u32x4_t& e0pre,
                                            const float (&bias4)[4], int ty0, int tx0, int wv,
                                            int r, int j, int g, int c16, bool sp) {
-  static_assert(C::BF && CO % 16 == 0, "pipelined pieces store bf16 NHWC rows");
-  (void)sp;  // SoftPlus only: bf16 passes of other activations take the direct kernel
+  static_assert((C::BF || C::SPLIT) && CO % 16 == 0, "pipelined pieces store NHWC rows");
+  (void)sp;  // SoftPlus only: passes of other activations take other kernels
   const int ly = wv * RW + r, oy = ty0 + ly, ox = tx0 + c16;
   const int co0 = 16 * j + 4 * g;
   float v[4];
@@ -369,18 +371,25 @@ __device__ inline void epilogue_piece_pipe(const ConvArgs& a, __amdgpu_buffer_rs
     const float x = accv[i];
     if constexpr (EPI == E_ACT) {
       const float hv = x + bias4[i];
-      v[i] = softplus_fast(hv);
+      v[i] = C::BF ? softplus_fast(hv) : softplus_hw(hv);
     } else if constexpr (EPI == E_DELTA) {
-      const float av = u2f((e0pre[i >> 1] << ((i & 1) ? 0 : 16)) & 0xffff0000u);
-      v[i] = dsp_from_a_fast(av) * x;
+      const float av = C::BF ? u2f((e0pre[i >> 1] << ((i & 1) ? 0 : 16)) & 0xffff0000u)
+                             : u2f(e0pre[i]);
+      v[i] = (C::BF ? dsp_from_a_fast(av) : dsp_from_a_hw(av)) * x;
     } else {
       v[i] = x;
     }
   }
-  const u32x2_v pk = {pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])};
   const bool ok = oy < a.H && ox < a.W;
-  const unsigned off = ok ? (static_cast<unsigned>(ly * a.W + ox) * CO + co0) * 2u : kDropOffset;
-  __builtin_amdgcn_raw_buffer_store_b64(pk, rs, static_cast<int>(off), 0, 0);
+  const unsigned eb = C::BF ? 2u : 4u;
+  const unsigned off = ok ? (static_cast<unsigned>(ly * a.W + ox) * CO + co0) * eb : kDropOffset;
+  if constexpr (C::BF) {
+    const u32x2_v pk = {pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])};
+    __builtin_amdgcn_raw_buffer_store_b64(pk, rs, static_cast<int>(off), 0, 0);
+  } else {
+    const u32x4_v pk = {f2u(v[0]), f2u(v[1]), f2u(v[2]), f2u(v[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(pk, rs, static_cast<int>(off), 0, 0);
+  }
 }
 
 template <int PREC, int CI, int CO, int PRO, int EPI>
@@ -392,6 +401,7 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
   // tile is issued in pieces between the matrix-core groups of the current one,
   // so its VALU work (SoftPlus / sigma', packing, stores) executes while the
   // MFMAs are in flight instead of after them
+  // (split kernels would need the row loop unrolled too, which spills)
   constexpr bool PIPE = C::ROWS && C::BF && CO % 16 == 0 &&
                         (EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW);
   constexpr int NPIECE = RW * C::NJ;
@@ -640,8 +650,8 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       {
         const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
         const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
-        prs = out_rsrc(static_cast<bf16*>(a.out0) + row0,
-                       static_cast<unsigned>(rows) * a.W * CO * 2u);
+        prs = out_rsrc(static_cast<char*>(a.out0) + row0 * C::GES,
+                       static_cast<unsigned>(rows) * a.W * CO * C::GES);
       }
     } else {
 #pragma unroll
@@ -709,6 +719,7 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
 #define IDQ_MFMA_THIN(X) X(16, 1) X(64, 3) X(32, 3)
 // split (hi/lo bf16) instantiations: the channel counts that are whole K chunks
 #define IDQ_MFMA_SPLIT(X) X(64, 64) X(32, 32) X(32, 64) X(64, 32)
+#define IDQ_MFMA_SPLIT_THIN(X) X(64, 3) X(32, 3)
 
 }  // namespace mfma
 }  // namespace idq
