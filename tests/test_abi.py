@@ -39,7 +39,8 @@ def test_version_and_defaults_without_gpu():
     o = _lib.SolveOpts()
     L.idq_solve_opts_default(C.byref(o))
     assert o.beta == 0.5 and o.lambda_ == 1.0 and o.tol == 1e-4 and o.conv_prec == _lib.IDQ_F32
-    assert o.switch_tol == 1e-3 and o.power_iters == 30 and o.init == _lib.IDQ_INIT_Y
+    assert o.switch_tol == 2e-3 and o.switch_patience == 5 and o.refine_prec == _lib.IDQ_F32
+    assert o.power_iters == 30 and o.init == _lib.IDQ_INIT_Y
 
 
 STRUCTS = {"NetDesc": "idq_net_desc", "OpDesc": "idq_op_desc", "SolveOpts": "idq_solve_opts",
