@@ -153,6 +153,8 @@ def main():
                     help="bf16 phase ends when rel < this ...")
     ap.add_argument("--patience", type=int, default=5,
                     help="... or after this many bf16 updates without a new best rel")
+    ap.add_argument("--poll", type=int, default=3,
+                    help="solver iterations enqueued between host polls of the phases")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel class inside the timed region (slower)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -191,7 +193,7 @@ def main():
     tau = 0.9 / L
     log(f"bench: L = {L:.6f}, tau = {tau:.6f} ({t_L * 1e3:.1f} ms, outside the timed region)")
 
-    common = dict(beta=0.5, tau=tau, lam=1.0, tol=1e-4, max_iter=2000)
+    common = dict(beta=0.5, tau=tau, lam=1.0, tol=1e-4, max_iter=2000, poll_every=args.poll)
     ws = None
     init = "y"
     if args.ws_weights and os.path.exists(args.ws_weights):

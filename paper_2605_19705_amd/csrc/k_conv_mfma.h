@@ -566,16 +566,23 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
             load_af(afn, aln, dxc, dy + 1);
           else if (dxc + 1 < 3 * C::CPT)
             load_af(afn, aln, dxc + 1, 0);
+          // split: small terms first (lo*hi, hi*lo, then hi*hi), each term over
+          // all accumulators before the next, so consecutive MFMAs never wait
+          // for one another's result
+          if (C::SPLIT) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], afc[j], browl[r + dy]);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], alc[j], brow[r + dy]);
+          }
 #pragma unroll
           for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int j = 0; j < C::NJ; ++j) {
-              if (C::SPLIT) {  // small terms first: lo*hi + hi*lo, then hi*hi
-                mma<C>(acc[r][j], afc[j], browl[r + dy]);
-                mma<C>(acc[r][j], alc[j], brow[r + dy]);
-              }
-              mma<C>(acc[r][j], afc[j], brow[r + dy]);
-            }
+            for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], afc[j], brow[r + dy]);
           piece_prev(dxc * 3 + dy);
 #pragma unroll
           for (int j = 0; j < C::NJ; ++j) afc[j] = afn[j];

@@ -1,0 +1,143 @@
+"""GPU checks at the full sizes the bench times.
+
+* Regularizer gradient on the 8 x 3 x 256 x 256 deblurring batch, compared with
+  the float64 oracle on sampled pixels.  The gradient at a pixel depends only on
+  the input within Chebyshev radius 10 (5 zero-padded 3x3 convs forward, 5 back),
+  so the oracle evaluates a 21 x 21 crop around each sample, clipped at the image
+  border (where the crop's zero padding is the image's own).
+* The headline solve (warm start, bf16 -> split-bf16 -> fp32) and the fp32-plain
+  solve at that size: both converge, end within the bf16 tolerance of each
+  other, and the headline ends on float32 updates.
+* The training-step backward at 16 x 3 x 128 x 128 (JFB against central
+  differences in theta of the regularizer gradient; implicit-mode properties).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import operators as O, regularizer as R
+
+from gpu_util import to_gpu, to_np, rel_err, net_layers
+
+pytestmark = pytest.mark.gpu
+
+RADIUS = 10
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2605_19705_amd", "weights", "warmstart_deblur.npy")
+
+
+def _deblur(cfg_id, n, size):
+    from paper_2605_19705_amd import IDQ
+    layers = net_layers("rgb64", 0)
+    taps = synth.gaussian_taps(9, 1.6)
+    xt, nz = synth.make_batch(cfg_id, n, 3, size, size)
+    y = O.Operator("blur", taps).A(xt) + 0.01 * nz
+    return layers, taps, xt, y, IDQ(layers, op_kind="blur", taps=taps, device=0)
+
+
+def _samples(n, h, w, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (n - 1, h - 1, w - 1), (0, 0, w - 1), (n - 1, h - 1, 0), (0, 3, w // 2),
+           (n // 2, h // 2, 9)]
+    while len(pts) < count:
+        pts.append((int(rng.integers(n)), int(rng.integers(h)), int(rng.integers(w))))
+    return pts
+
+
+def _oracle_grad_at(net, x, n, py, px):
+    h, w = x.shape[2:]
+    y0, y1 = max(0, py - RADIUS), min(h, py + RADIUS + 1)
+    x0, x1 = max(0, px - RADIUS), min(w, px + RADIUS + 1)
+    g = net.grad(x[n:n + 1, :, y0:y1, x0:x1])
+    return g[0, :, py - y0, px - x0]
+
+
+def test_grad_reg_full_size_sampled():
+    print("grad_reg at 8x3x256x256 vs oracle crops, f64 / f32 / bf16x3 / bf16", flush=True)
+    layers, taps, xt, y, ctx = _deblur(2, 8, 256)
+    net = R.Net(layers)
+    pts = _samples(8, 256, 256, 24, seed=7)
+    ref = np.stack([_oracle_grad_at(net, y, *p) for p in pts])          # (samples, 3)
+    pick = lambda g: np.stack([g[n, :, py, px] for n, py, px in pts])   # noqa: E731
+    g64 = pick(to_np(ctx.grad_reg(to_gpu(y))))
+    assert np.max(np.abs(g64 - ref)) < 1e-10
+    y32 = to_gpu(y, torch.float32)
+    for prec in ("f32", "bf16x3"):
+        g = pick(to_np(ctx.grad_reg(y32, conv_prec=prec)))
+        assert np.max(np.abs(g - ref)) < 1e-4, prec
+    g = pick(to_np(ctx.grad_reg(y32, conv_prec="bf16")))
+    assert np.linalg.norm(g - ref) < 2e-2 * np.linalg.norm(ref)
+
+
+def test_headline_and_fp32_solves_full_size():
+    print("headline and fp32-plain solves at 8x3x256x256", flush=True)
+    from paper_2605_19705_amd import WarmStart
+    layers, taps, xt, y, ctx = _deblur(2, 8, 256)
+    yg = to_gpu(y, torch.float32)
+    v0 = to_gpu(synth.random_field(12345, y.shape), torch.float32)
+    tau = 0.9 / ctx.lipschitz(yg, yg, v0, lam=1.0, iters=30, conv_prec="f32")
+    ws = WarmStart(np.load(WEIGHTS).astype(np.float64), device=0)
+    common = dict(beta=0.5, tau=tau, lam=1.0, tol=1e-4, max_iter=2000)
+    xh, rh = ctx.solve(yg, conv_prec="bf16", refine_prec="bf16x3", init="warmstart", ws=ws,
+                       ws_prec="bf16", poll_every=3, **common)
+    xf, rf = ctx.solve(yg, conv_prec="f32", **common)
+    for r in (rh, rf):
+        assert np.all(r.status == 0) and np.all(r.rel < 1e-4)
+    assert np.all(rh.iters > rh.iters_low + rh.iters_mid)
+    assert np.all(rh.iters_low > 0) and np.all(rh.iters_mid > 0)
+    assert rel_err(to_np(xh), to_np(xf)) < 2e-2
+
+
+def test_training_step_backward_full_size():
+    """Backward at the training-step size (16 x 3 x 128 x 128).  At this size the
+    adjoint fixed-point iteration contracts only at 1 - tau mu_min of the
+    deblurring Hessian (the 3 x 8 x 8 problem of test_backward_parity_on_crop
+    pins the converged implicit gradient), so here:
+    * JFB's theta gradient against central differences in theta of the float64
+      regularizer gradient at the fixed point, <dtheta, d> = -tau lambda
+      <v, d/de grad g_{theta + e d}(x_bar)>, and JFB's dlambda = -tau <grad g, v>;
+    * implicit with 0 adjoint iterations is JFB; more iterations lower the
+      adjoint residual."""
+    print("backward at 16x3x128x128: JFB vs FD of grad g in theta, implicit", flush=True)
+    from paper_2605_19705_amd import pack_layers
+    layers, taps, xt, y, ctx = _deblur(4, 16, 128)
+    yg = to_gpu(y, torch.float32)
+    v0 = to_gpu(synth.random_field(12345, y.shape), torch.float32)
+    tau = 0.9 / ctx.lipschitz(yg, yg, v0, lam=1.0, iters=30, conv_prec="f32")
+    xb, rb = ctx.solve(yg, beta=0.5, tau=tau, lam=1.0, tol=1e-6, max_iter=5000, conv_prec="f32")
+    assert np.all(rb.status == 0)
+    xbar = to_np(xb)
+    v = 2.0 * (xbar - xt) / xbar.size
+    vg = to_gpu(v, torch.float32)
+    dj, dlj, _ = ctx.backward(xb, yg, vg, tau, 1.0, mode="jfb")
+    gj = to_np(dj.reshape(1, 1, 1, -1)).ravel()
+    assert np.all(np.isfinite(gj))
+    x64 = to_gpu(xbar)
+    gq = to_np(ctx.grad_reg(x64))
+    assert abs(dlj - (-tau * float(np.sum(gq * v)))) < 1e-4 * abs(dlj)
+    theta = pack_layers(layers)
+    rng = np.random.default_rng(11)
+    eps = 1e-4
+    for _ in range(2):
+        d = rng.standard_normal(theta.size)
+        d *= np.linalg.norm(theta) / np.linalg.norm(d)
+        ctx.set_params(theta + eps * d)
+        gp = to_np(ctx.grad_reg(x64))
+        ctx.set_params(theta - eps * d)
+        gm = to_np(ctx.grad_reg(x64))
+        ctx.set_params(theta)
+        fd = -tau * 1.0 * float(np.sum(v * (gp - gm))) / (2 * eps)
+        an = float(np.dot(gj, d))
+        assert abs(fd - an) < 1e-3 * abs(fd), (fd, an)
+    # implicit: 0 adjoint iterations is JFB; the residual falls with more
+    d0, dl0, (it0, _) = ctx.backward(xb, yg, vg, tau, 1.0, mode="implicit", adjoint_max_iter=0)
+    assert it0 == 0 and np.array_equal(to_np(d0), to_np(dj)) and dl0 == dlj
+    _, _, (i1, r1) = ctx.backward(xb, yg, vg, tau, 1.0, mode="implicit", adjoint_max_iter=50,
+                                  adjoint_tol=0.0, adjoint_beta=0.5)
+    d2, dl2, (i2, r2) = ctx.backward(xb, yg, vg, tau, 1.0, mode="implicit", adjoint_max_iter=400,
+                                     adjoint_tol=0.0, adjoint_beta=0.5)
+    assert i1 == 50 and i2 == 400 and r2 < r1
+    assert np.all(np.isfinite(to_np(d2))) and np.isfinite(dl2)
