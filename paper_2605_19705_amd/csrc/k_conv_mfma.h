@@ -40,10 +40,8 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4_t;
 
-constexpr int kThreads = 256;
 constexpr int TH = 16, TW = 16;
 constexpr int HW_ = TW + 2, HH_ = TH + 2, NPIX = HW_ * HH_;
-constexpr int RW = 4;  // output rows per wave
 
 template <int PREC, int CI, int CO>
 struct Cfg {
@@ -66,13 +64,25 @@ struct Cfg {
   static constexpr int LO_OFF = CIP * ES;
   static constexpr int PIXB = (SPLIT ? 2 : 1) * CIP * ES + (VEC ? 16 : 0);
   static constexpr int LDS_IN = (NPIX * PIXB + 15) / 16 * 16;
-  static constexpr bool WLDS = MBF;            // (split: the hi fragments; lo from L2)
-  static constexpr int WBYTES = NCH * NJ * 64 * 16;
-  static constexpr int LDS = LDS_IN + (WLDS ? WBYTES : 0);
+  // launch shape: 4 waves of 4 output rows, one workgroup per tile; the split
+  // 64 -> 64 passes instead run 8 waves of 2 rows (two waves per SIMD, so one
+  // wave's matrix-core work overlaps the other's staging and epilogue) and give
+  // each of two workgroups per tile half of the output channels, so that both
+  // the hi and the lo weight fragments of that half fit in LDS beside the tile
+  static constexpr bool WIDE8 = SPLIT && CI == 64 && CO == 64;
+  static constexpr int WAVES = WIDE8 ? 8 : 4;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int RWV = TH / WAVES;         // output rows per wave
+  static constexpr int CSPLIT = WIDE8 ? 2 : 1;   // workgroups (channel groups) per tile
+  static constexpr int NJW = NJ / CSPLIT;        // 16-channel blocks per workgroup
+  static constexpr bool WLDS = MBF;              // hi (bf16, split) fragments in LDS
+  static constexpr bool WLO_LDS = WIDE8;         // split lo fragments in LDS too (else L2)
+  static constexpr int WBYTES = NCH * NJW * 64 * 16;
+  static constexpr int LDS = LDS_IN + (WLDS ? WBYTES * (WLO_LDS ? 2 : 1) : 0);
   // prefetch: 16-byte items (VEC) or floats (gather) per thread for one tile
   static constexpr int VPP = VEC ? CI / GV : 0;
-  static constexpr int ITEMS = VEC ? (NPIX * VPP + kThreads - 1) / kThreads
-                                   : (NPIX * CI + kThreads - 1) / kThreads;
+  static constexpr int ITEMS = VEC ? (NPIX * VPP + THREADS - 1) / THREADS
+                                   : (NPIX * CI + THREADS - 1) / THREADS;
   // fp32 reads its weights from global memory: a short unroll keeps the
   // hoisted loads within the register file
   static constexpr int UNROLL = MBF ? NCH : 2;
@@ -80,6 +90,7 @@ struct Cfg {
   // bf16; one for split operands, whose doubled fragments would spill otherwise
   static constexpr int RUNROLL = BF ? 3 * CPT : 1;
   static_assert(!SPLIT || (VEC && ROWS), "split operands need whole K chunks per tap");
+  static_assert(NJ % CSPLIT == 0 && TH % WAVES == 0, "launch shape");
 };
 
 __device__ inline unsigned pack2(bf16 lo, bf16 hi) {
@@ -116,7 +127,7 @@ struct Prefetch {
 // Epilogue operand of one tile (E_DELTA): 4 channels per (row, channel block).
 template <class C>
 struct EpiPrefetch {
-  u32x4_t v[RW][C::NJ];
+  u32x4_t v[C::RWV][C::NJW];
 };
 
 template <class C, int CI, int PRO>
@@ -124,7 +135,7 @@ __device__ inline void load_tile(const ConvArgs& a, Prefetch<C, PRO>& pf, int ni
                                  int tx0, int tid) {
 #pragma unroll
   for (int k = 0; k < C::ITEMS; ++k) {
-    const int it = tid + k * kThreads;
+    const int it = tid + k * C::THREADS;
     if (C::VEC) {
       u32x4_t val = {0u, 0u, 0u, 0u}, hd = {0u, 0u, 0u, 0u};
       if (it < NPIX * C::VPP) {
@@ -159,7 +170,7 @@ __device__ inline void store_tile(const ConvArgs& a, const Prefetch<C, PRO>& pf,
   const bool sp = a.act == IDQ_ACT_SOFTPLUS;
 #pragma unroll
   for (int k = 0; k < C::ITEMS; ++k) {
-    const int it = tid + k * kThreads;
+    const int it = tid + k * C::THREADS;
     if (C::VEC) {
       if (it < NPIX * C::VPP) {
         const int p = it / C::VPP, v = it - (it / C::VPP) * C::VPP;
@@ -230,7 +241,7 @@ __device__ inline void epilogue_piece(const ConvArgs& a, const f32x4_t& accv,
                                       const u32x4_t& e0pre, const float (&bias4)[4], int ni,
                                       int ty0, int tx0, int wv, int r, int j, int g, int c16,
                                       bool sp) {
-  const int oy = ty0 + wv * RW + r, ox = tx0 + c16;
+  const int oy = ty0 + wv * C::RWV + r, ox = tx0 + c16;
   if (oy >= a.H || ox >= a.W) return;
   const int co0 = 16 * j + 4 * g;
   if (co0 >= CO) return;
@@ -363,7 +374,7 @@ __device__ inline void epilogue_piece_pipe(const ConvArgs& a, __amdgpu_buffer_rs
                                            int r, int j, int g, int c16, bool sp) {
   static_assert((C::BF || C::SPLIT) && CO % 16 == 0, "pipelined pieces store NHWC rows");
   (void)sp;  // SoftPlus only: passes of other activations take other kernels
-  const int ly = wv * RW + r, oy = ty0 + ly, ox = tx0 + c16;
+  const int ly = wv * C::RWV + r, oy = ty0 + ly, ox = tx0 + c16;
   const int co0 = 16 * j + 4 * g;
   float v[4];
 #pragma unroll
@@ -393,8 +404,8 @@ __device__ inline void epilogue_piece_pipe(const ConvArgs& a, __amdgpu_buffer_rs
 }
 
 template <int PREC, int CI, int CO, int PRO, int EPI>
-__global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int ntx, int nty,
-                                                               int ntiles) {
+__global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_kernel(
+    ConvArgs a, int ntx, int nty, int ntiles) {
   using C = Cfg<PREC, CI, CO>;
   static_assert(!C::SPLIT || PRO == P_NONE, "split passes take plain operands");
   // bf16 row-reuse kernels run software-pipelined: the epilogue of the previous
@@ -404,11 +415,13 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
   // (split kernels would need the row loop unrolled too, which spills)
   constexpr bool PIPE = C::ROWS && C::BF && CO % 16 == 0 &&
                         (EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW);
-  constexpr int NPIECE = RW * C::NJ;
+  constexpr int RW = C::RWV, NJW = C::NJW;
+  constexpr int NPIECE = RW * NJW;
   constexpr bool pre_e0 = EPI == E_DELTA && CO % 4 == 0;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   char* lin = smem;
   const u32x4_t* lw = reinterpret_cast<const u32x4_t*>(smem + C::LDS_IN);
+  const u32x4_t* lwl = lw + C::NCH * NJW * 64;     // split lo fragments in LDS (WLO_LDS)
   const u32x4_t* gw = static_cast<const u32x4_t*>(a.wmfma);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, c16 = lane & 15;
@@ -418,11 +431,14 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
     return gate_open_uniform(a.gate, a.gate_mask, (t / tiles_per_img) / a.img_div);
   };
 
+  // channel group of this workgroup and its walk over the tiles
+  const int jh = C::CSPLIT > 1 ? static_cast<int>(blockIdx.x) % C::CSPLIT : 0;
+  const int tstep = static_cast<int>(gridDim.x) / C::CSPLIT;
   // first open tile of this workgroup (uniform across it); a workgroup with
   // none leaves before staging weights, so a pass whose images are all in
   // another precision phase costs little more than its launch
-  int t = blockIdx.x;
-  while (t < ntiles && !open(t)) t += gridDim.x;
+  int t = static_cast<int>(blockIdx.x) / C::CSPLIT;
+  while (t < ntiles && !open(t)) t += tstep;
   if (t >= ntiles) return;
 
   // the first tile's halo is requested before the weights, and the weight
@@ -434,50 +450,58 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
     load_tile<C, CI, PRO>(a, pf, ni, (rem / ntx) * TH, (rem % ntx) * TW, tid);
   }
   if (C::WLDS) {
-    constexpr int NW = C::NCH * C::NJ * 64;          // 16-byte fragments
-    constexpr int PER = (NW + kThreads - 1) / kThreads;
+    // LDS fragment i = (ch * NJW + jj) * 64 + lane of this workgroup's channel
+    // blocks; the lo parts (WLO_LDS) follow the hi parts
+    constexpr int NW = C::NCH * NJW * 64;            // 16-byte fragments per part
+    constexpr int NT = NW * (C::WLO_LDS ? 2 : 1);
+    constexpr int PER = (NT + C::THREADS - 1) / C::THREADS;
     constexpr int WB = PER < 24 ? PER : 24;
     u32x4_t* dst = reinterpret_cast<u32x4_t*>(smem + C::LDS_IN);
+    auto src = [&](int i) {
+      const int part = i >= NW ? 1 : 0, f = i - part * NW;
+      const int ln = f % 64, jj = (f / 64) % NJW, ch = f / (64 * NJW);
+      return (part * C::NCH * C::NJ + ch * C::NJ + jh * NJW + jj) * 64 + ln;
+    };
     for (int b0 = 0; b0 < PER; b0 += WB) {
       u32x4_t wbuf[WB];
 #pragma unroll
       for (int q = 0; q < WB; ++q) {
-        const int i = tid + (b0 + q) * kThreads;
-        if (i < NW) wbuf[q] = gw[i];
+        const int i = tid + (b0 + q) * C::THREADS;
+        if (i < NT) wbuf[q] = gw[src(i)];
       }
 #pragma unroll
       for (int q = 0; q < WB; ++q) {
-        const int i = tid + (b0 + q) * kThreads;
-        if (i < NW) dst[i] = wbuf[q];
+        const int i = tid + (b0 + q) * C::THREADS;
+        if (i < NT) dst[i] = wbuf[q];
       }
     }
   }
 
-  // bias of the 16 output channels this lane owns in the epilogue
-  float bias_r[C::NJ][4];
+  // bias of the output channels this lane owns in the epilogue
+  float bias_r[NJW][4];
   {
     const float* bias = static_cast<const float*>(a.bias);
 #pragma unroll
-    for (int j = 0; j < C::NJ; ++j)
+    for (int jj = 0; jj < NJW; ++jj)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int co = 16 * j + 4 * g + i;
-        bias_r[j][i] = (bias && co < CO) ? bias[co] : 0.f;
+        const int co = 16 * (jh * NJW + jj) + 4 * g + i;
+        bias_r[jj][i] = (bias && co < CO) ? bias[co] : 0.f;
       }
   }
 
   // the previous tile (PIPE): accumulators, epilogue operand, position and
   // the output resource over its rows (none before the first tile)
-  f32x4_t accp[PIPE ? RW : 1][PIPE ? C::NJ : 1];
+  f32x4_t accp[PIPE ? RW : 1][PIPE ? NJW : 1];
   EpiPrefetch<C> epp;
   int pty0 = 0, ptx0 = 0;
   __amdgpu_buffer_rsrc_t prs = out_rsrc(a.out0, 0u);
   auto piece_prev = [&](int k) {
     if constexpr (PIPE) {
       if (k < NPIECE) {
-        const int r = k / C::NJ, j = k % C::NJ;
-        epilogue_piece_pipe<C, CO, EPI>(a, prs, accp[r][j], epp.v[r][j], bias_r[j], pty0, ptx0,
-                                        wv, r, j, g, c16, sp);
+        const int r = k / NJW, jj = k % NJW;
+        epilogue_piece_pipe<C, CO, EPI>(a, prs, accp[r][jj], epp.v[r][jj], bias_r[jj], pty0,
+                                        ptx0, wv, r, jh * NJW + jj, g, c16, sp);
       }
     }
   };
@@ -489,13 +513,13 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
     __syncthreads();  // the previous tile's fragments have been read
     store_tile<C, CI, PRO>(a, pf, lin, tid);
     __syncthreads();
-    int tn = t + gridDim.x;
-    while (tn < ntiles && !open(tn)) tn += gridDim.x;
+    int tn = t + tstep;
+    while (tn < ntiles && !open(tn)) tn += tstep;
     if (tn < ntiles) {
       const int nn = tn / tiles_per_img, rn = tn - nn * tiles_per_img;
       load_tile<C, CI, PRO>(a, pf, nn, (rn / ntx) * TH, (rn % ntx) * TW, tid);
     }
-    if (a.work_px && tid == 0) {
+    if (a.work_px && tid == 0 && jh == 0) {
       const int vh = a.H - ty0 < TH ? a.H - ty0 : TH, vw = a.W - tx0 < TW ? a.W - tx0 : TW;
       atomicAdd(a.work_px, static_cast<unsigned long long>(vh * vw));
     }
@@ -507,46 +531,49 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
       for (int r = 0; r < RW; ++r) {
         const int oy = ty0 + wv * RW + r, ox = tx0 + c16;
 #pragma unroll
-        for (int j = 0; j < C::NJ; ++j) {
-          const int co0 = 16 * j + 4 * g;
-          ep.v[r][j] = u32x4_t{0u, 0u, 0u, 0u};
+        for (int jj = 0; jj < NJW; ++jj) {
+          const int co0 = 16 * (jh * NJW + jj) + 4 * g;
+          ep.v[r][jj] = u32x4_t{0u, 0u, 0u, 0u};
           if (oy < a.H && ox < a.W && co0 < CO) {
             const size_t o = ((static_cast<size_t>(ni) * a.H + oy) * a.W + ox) * CO + co0;
             if (C::BF) {
               const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const bf16*>(a.e0) + o);
-              ep.v[r][j] = u32x4_t{u.x, u.y, 0u, 0u};
+              ep.v[r][jj] = u32x4_t{u.x, u.y, 0u, 0u};
             } else {
-              ep.v[r][j] = *reinterpret_cast<const u32x4_t*>(static_cast<const float*>(a.e0) + o);
+              ep.v[r][jj] = *reinterpret_cast<const u32x4_t*>(static_cast<const float*>(a.e0) + o);
             }
           }
         }
       }
     }
     // ---- K loop on the matrix cores ------------------------------------------
-    f32x4_t acc[RW][C::NJ];
+    f32x4_t acc[RW][NJW];
 #pragma unroll
     for (int r = 0; r < RW; ++r)
 #pragma unroll
-      for (int j = 0; j < C::NJ; ++j) acc[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < NJW; ++j) acc[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     if (C::ROWS) {
       // k = (dy*3 + dx) * CI + c*KC + slice: load the RW+2 input rows once per
       // (dx, c) and reuse them for dy = 0, 1, 2.  The weight fragments of the
       // next (dx, c, dy) group are fetched while the current group's MFMAs
       // run (for fp32 they come from L2, whose latency would otherwise stall
       // every group).
-      constexpr int NL = C::SPLIT ? C::NJ : 1;
-      const u32x4_t* gwl = gw + C::NCH * C::NJ * 64;  // split: lo fragments
+      constexpr int NL = C::SPLIT ? NJW : 1;
+      const u32x4_t* gwl = gw + C::NCH * C::NJ * 64;  // split: lo fragments in L2
+      // fragments of this workgroup's channel blocks: LDS holds only those
+      // (index ch * NJW + jj); global memory holds all NJ (CSPLIT is 1 there)
       auto load_af = [&](u32x4_t* dst, u32x4_t* dlo, int dxc, int dy) {
         const int ch = (dy * 3 + dxc / C::CPT) * C::CPT + dxc % C::CPT;
 #pragma unroll
-        for (int j = 0; j < C::NJ; ++j) dst[j] = C::WLDS ? lw[(ch * C::NJ + j) * 64 + lane]
-                                                      : gw[(ch * C::NJ + j) * 64 + lane];
+        for (int j = 0; j < NJW; ++j) dst[j] = C::WLDS ? lw[(ch * NJW + j) * 64 + lane]
+                                                    : gw[(ch * C::NJ + j) * 64 + lane];
         if (C::SPLIT) {
 #pragma unroll
-          for (int j = 0; j < C::NJ; ++j) dlo[j] = gwl[(ch * C::NJ + j) * 64 + lane];
+          for (int j = 0; j < NJW; ++j) dlo[j] = C::WLO_LDS ? lwl[(ch * NJW + j) * 64 + lane]
+                                                         : gwl[(ch * C::NJ + j) * 64 + lane];
         }
       };
-      u32x4_t afc[C::NJ], afn[C::NJ], alc[NL], aln[NL];
+      u32x4_t afc[NJW], afn[NJW], alc[NL], aln[NL];
       load_af(afc, alc, 0, 0);
 #pragma unroll C::RUNROLL
       for (int dxc = 0; dxc < 3 * C::CPT; ++dxc) {
@@ -573,22 +600,22 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
 #pragma unroll
             for (int r = 0; r < RW; ++r)
 #pragma unroll
-              for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], afc[j], browl[r + dy]);
+              for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], browl[r + dy]);
 #pragma unroll
             for (int r = 0; r < RW; ++r)
 #pragma unroll
-              for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], alc[j], brow[r + dy]);
+              for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], alc[j], brow[r + dy]);
           }
 #pragma unroll
           for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], afc[j], brow[r + dy]);
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], brow[r + dy]);
           piece_prev(dxc * 3 + dy);
 #pragma unroll
-          for (int j = 0; j < C::NJ; ++j) afc[j] = afn[j];
+          for (int j = 0; j < NJW; ++j) afc[j] = afn[j];
           if (C::SPLIT) {
 #pragma unroll
-            for (int j = 0; j < C::NJ; ++j) alc[j] = aln[j];
+            for (int j = 0; j < NJW; ++j) alc[j] = aln[j];
           }
         }
       }
@@ -596,10 +623,11 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
 #pragma unroll C::UNROLL
       for (int ch = 0; ch < C::NCH; ++ch) {
         const int kb = ch * C::KC + g * C::V;
-        u32x4_t af[C::NJ];
+        static_assert(C::CSPLIT == 1 || C::ROWS, "channel groups need the row-reuse path");
+        u32x4_t af[NJW];
 #pragma unroll
-        for (int j = 0; j < C::NJ; ++j) af[j] = C::WLDS ? lw[(ch * C::NJ + j) * 64 + lane]
-                                                     : gw[(ch * C::NJ + j) * 64 + lane];
+        for (int j = 0; j < NJW; ++j) af[j] = C::WLDS ? lw[(ch * NJW + j) * 64 + lane]
+                                                   : gw[(ch * C::NJ + j) * 64 + lane];
         u32x4_t bfr[RW];
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
@@ -637,7 +665,7 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
 #pragma unroll
         for (int r = 0; r < RW; ++r)
 #pragma unroll
-          for (int j = 0; j < C::NJ; ++j) mma<C>(acc[r][j], af[j], bfr[r]);
+          for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], af[j], bfr[r]);
       }
     }
     // ---- epilogue ----------------------------------------------------------------
@@ -648,7 +676,7 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
 #pragma unroll
       for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int j = 0; j < C::NJ; ++j) {
+        for (int j = 0; j < NJW; ++j) {
           accp[r][j] = acc[r][j];
           epp.v[r][j] = ep.v[r][j];
         }
@@ -664,9 +692,9 @@ __global__ __launch_bounds__(kThreads, 1) void conv_mfma_kernel(ConvArgs a, int 
 #pragma unroll
       for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int j = 0; j < C::NJ; ++j)
-          epilogue_piece<C, CO, EPI>(a, acc[r][j], ep.v[r][j], bias_r[j], ni, ty0, tx0, wv, r, j,
-                                     g, c16, sp);
+        for (int j = 0; j < NJW; ++j)
+          epilogue_piece<C, CO, EPI>(a, acc[r][j], ep.v[r][j], bias_r[j], ni, ty0, tx0, wv, r,
+                                     jh * NJW + j, g, c16, sp);
     }
     t = tn;
   }
@@ -691,7 +719,7 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
     int dev = 0, ncu = 0, occ = 0;
     IDQ_HIP(hipGetDevice(&dev));
     IDQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    IDQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, C::LDS));
+    IDQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, C::THREADS, C::LDS));
     if (occ < 1) return fail(IDQ_E_UNSUPPORTED, "MFMA conv does not fit on a compute unit");
     max_blocks = ncu * occ;
     attr_set = true;
@@ -704,15 +732,17 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
   const long long nt = static_cast<long long>(a.NI) * ntx * nty;
   if (nt > 0x7fffffff) return fail(IDQ_E_INVAL, "too many tiles");
   const int ntiles = static_cast<int>(nt);
-  const int grid = ntiles < max_blocks ? ntiles : max_blocks;
+  // tile walkers (each CSPLIT workgroups, one per channel group), all resident
+  const int walkers_max = max_blocks / C::CSPLIT > 0 ? max_blocks / C::CSPLIT : 1;
+  const int grid = (ntiles < walkers_max ? ntiles : walkers_max) * C::CSPLIT;
   if (a.ev0) {
     ConvArgs ac = a;
     int nx = ntx, ny = nty, ntl = ntiles;
     void* args[] = {&ac, &nx, &ny, &ntl};
-    IDQ_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(kThreads),
-                               args, C::LDS, s, a.ev0, a.ev1, 0));
+    IDQ_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                               dim3(C::THREADS), args, C::LDS, s, a.ev0, a.ev1, 0));
   } else {
-    kern<<<grid, kThreads, C::LDS, s>>>(a, ntx, nty, ntiles);
+    kern<<<grid, C::THREADS, C::LDS, s>>>(a, ntx, nty, ntiles);
   }
   IDQ_HIP(hipGetLastError());
   return IDQ_OK;
