@@ -34,21 +34,27 @@ METRIC = "restored 256^2 images/s at rel. residual 1e-4: BF16+warm-start vs FP32
 BF16_PEAK = 2.5e15     # MI355X dense bf16 matrix-core peak, FLOP/s
 F32_PEAK = 157.3e12    # MI355X dense fp32 matrix-core peak, FLOP/s
 FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
-# HBM bytes per launch of the bf16 64->64 conv kernel in this solve, from the
-# FETCH_SIZE / WRITE_SIZE counter runs summarised in
-# profiles/conv_bf16_64x64_deblur_8x3x256_hbm_counters.md (FETCH x 2.0, WRITE x 1.0,
-# the factors a 256 MiB device copy gives); valid only while the kernel's device
-# code is the one measured (sha256 of its two sources below), else reported as null.
-TRAFFIC_BYTES_PER_LAUNCH = 123247461
-TRAFFIC_SOURCES = ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
-                   "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")
-TRAFFIC_SHA256 = "1b920598a8d757a8c4436599800bafd3c537c23d674c5b5deb56ddbff6476a51"
+# HBM bytes per launch of the 64->64 conv kernels in this solve, from the
+# FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/ (FETCH x 2.0,
+# WRITE x 1.0, the factors a 256 MiB device copy gives); a figure is valid only
+# while the kernel's device code is the one measured (sha256 of its sources),
+# else it is reported as null.
+TRAFFIC = {
+    "conv64_bf16": {"bytes": 154664816,
+                    "sha256": "b0d5248e152f164a498ae52e915d6786c0e23caa5997cab127b7fffca2e1844f",
+                    "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
+                                "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
+    "conv64_bf16x3": {"bytes": 218101403,
+                      "sha256": "4861daa9f69293691e242f9004d205a3e447979297ff5a288e367da569208805",
+                      "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
+                                  "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},
+}
 
 
-def sources_sha256():
+def sources_sha256(sources):
     import hashlib
     h = hashlib.sha256()
-    for p in TRAFFIC_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -142,8 +148,8 @@ def cpu_baseline(iters_per_image, sample_iters=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32-plain arm")
     ap.add_argument("--refine", default="bf16x3", choices=["f32", "bf16x3"],
@@ -207,7 +213,8 @@ def main():
     log(f"bench: headline arm (bf16 + fp32 refinement, init={init}), "
         f"{args.warmup} warmup + {args.steps} timed solves")
     head = time_arm(torch, ctx, y, args.steps, args.warmup,
-                    profile=PROF_CLASSES if args.profile_all else ["conv64_bf16"], **head_kw)
+                    profile=PROF_CLASSES if args.profile_all else ["conv64_bf16", "conv64_bf16x3"],
+                    **head_kw)
     n_img = y.shape[0]
     value = n_img * args.steps / head["total_s"]
     log(f"bench: headline {value:.2f} images/s, iterations {head['iters'][-1]}, "
@@ -220,21 +227,35 @@ def main():
         fp32["value"] = n_img * len(fp32["step_s"]) / fp32["total_s"]
         log(f"bench: fp32 plain {fp32['value']:.2f} images/s, iterations {fp32['iters'][-1]}")
 
-    # roofline of the dominant kernel: the 64->64 bf16 conv passes of the timed solves
-    ms, launches, px = head["prof"]["conv64_bf16"]
-    avg_ms = ms / max(launches, 1)
-    flops_per_launch = FLOP_PER_PX_64 * px / max(launches, 1)
-    achieved = flops_per_launch / (avg_ms * 1e-3) if launches else 0.0
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK,
-                "traffic": TRAFFIC_BYTES_PER_LAUNCH if sources_sha256() == TRAFFIC_SHA256 else None,
+    # rooflines of the 64->64 conv kernels of the timed solves; the dominant one
+    # (by device time) is `roofline`, the other `roofline_other`
+    def conv_roofline(cls):
+        ms, launches, px = head["prof"][cls]
+        if not launches:
+            return None
+        split = cls == "conv64_bf16x3"
+        avg_ms = ms / launches
+        flops_per_launch = FLOP_PER_PX_64 * px / launches
+        achieved = flops_per_launch / (avg_ms * 1e-3)
+        # split-bf16 runs three bf16 products per term: its ceiling is a third of
+        # the bf16 matrix-core peak, in the conv's own flops
+        peak = BF16_PEAK / 3.0 if split else BF16_PEAK
+        tr = TRAFFIC[cls]
+        # bytes per pixel of an E_ACT pass (in + out) and an E_DELTA pass
+        # (in + sigma operand + out), which the solve runs in equal numbers
+        per_px = (512.0 + 768.0) / 2 if split else (256.0 + 384.0) / 2
+        return {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": tr["bytes"] if sources_sha256(tr["sources"]) == tr["sha256"] else None,
                 "traffic_unit": "bytes per launch",
-                # E_ACT passes move 128 B in + 128 B out per pixel, E_DELTA 256 + 128;
-                # the solve runs them in equal numbers
-                "algorithmic_bytes": 320.0 * px / max(launches, 1),
-                "kernel": "conv_mfma_kernel<bf16, 64, 64>", "launches": launches,
-                "avg_launch_us": avg_ms * 1e3,
-                "flop_per_launch": flops_per_launch}
+                "algorithmic_bytes": per_px * px / launches,
+                "kernel": "conv_mfma_kernel<%s, 64, 64>" % ("bf16x3" if split else "bf16"),
+                "launches": launches, "avg_launch_us": avg_ms * 1e3,
+                "total_ms": ms, "flop_per_launch": flops_per_launch}
+    rl = {c: conv_roofline(c) for c in ("conv64_bf16x3", "conv64_bf16")}
+    order = sorted((r for r in rl.values() if r), key=lambda r: -r["total_ms"])
+    roofline = order[0]
+    roofline_other = order[1] if len(order) > 1 else None
     phases = class_breakdown(torch, ctx, y, **head_kw)
 
     cpu = None
@@ -275,6 +296,7 @@ def main():
         "step_size": {"L": L, "tau": tau, "power_iteration_ms": t_L * 1e3},
         "device_ms_by_class_one_solve": phases,
         "roofline": roofline,
+        "roofline_other": roofline_other,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -31,6 +31,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace idq {
@@ -412,7 +414,8 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
   // tile is issued in pieces between the matrix-core groups of the current one,
   // so its VALU work (SoftPlus / sigma', packing, stores) executes while the
   // MFMAs are in flight instead of after them
-  // (split kernels would need the row loop unrolled too, which spills)
+  // (bf16 only: the 8-wave split shape already overlaps one wave's epilogue
+  // with the other's matrix-core work, and pieces there measured slower)
   constexpr bool PIPE = C::ROWS && C::BF && CO % 16 == 0 &&
                         (EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW);
   constexpr int RW = C::RWV, NJW = C::NJW;
@@ -431,13 +434,27 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
     return gate_open_uniform(a.gate, a.gate_mask, (t / tiles_per_img) / a.img_div);
   };
 
-  // channel group of this workgroup and its walk over the tiles
-  const int jh = C::CSPLIT > 1 ? static_cast<int>(blockIdx.x) % C::CSPLIT : 0;
+  // channel group of this workgroup and its walk over the tiles.  Workgroups
+  // go to the 8 XCDs round-robin by index, each XCD with its own L2: the
+  // channel groups of one tile are blocks b and b + 8 (same XCD), so the second
+  // read of the halo tile can hit that L2 (when the grid is a multiple of 16)
+  int jh = 0, walker = static_cast<int>(blockIdx.x);
+  if (C::CSPLIT > 1) {
+    const int b = static_cast<int>(blockIdx.x);
+    if (gridDim.x % (8 * C::CSPLIT) == 0) {
+      const int grp = b / 8;
+      jh = grp % C::CSPLIT;
+      walker = (grp / C::CSPLIT) * 8 + b % 8;
+    } else {
+      jh = b % C::CSPLIT;
+      walker = b / C::CSPLIT;
+    }
+  }
   const int tstep = static_cast<int>(gridDim.x) / C::CSPLIT;
   // first open tile of this workgroup (uniform across it); a workgroup with
   // none leaves before staging weights, so a pass whose images are all in
   // another precision phase costs little more than its launch
-  int t = static_cast<int>(blockIdx.x) / C::CSPLIT;
+  int t = walker;
   while (t < ntiles && !open(t)) t += tstep;
   if (t >= ntiles) return;
 
@@ -575,8 +592,9 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
       };
       u32x4_t afc[NJW], afn[NJW], alc[NL], aln[NL];
       load_af(afc, alc, 0, 0);
-#pragma unroll C::RUNROLL
-      for (int dxc = 0; dxc < 3 * C::CPT; ++dxc) {
+      // one (dx, chunk) step: its RW+2 input rows, then the three dy groups;
+      // WITH_PIECES puts a piece of the previous tile's epilogue after each group
+      auto dxc_step = [&](int dxc, auto with_pieces) {
         const int dx = dxc / C::CPT, c = dxc % C::CPT;
         u32x4_t brow[RW + 2], browl[C::SPLIT ? RW + 2 : 1];
         const int coff = (c * C::KC + g * C::V) * C::ES;
@@ -610,7 +628,7 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
           for (int r = 0; r < RW; ++r)
 #pragma unroll
             for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], brow[r + dy]);
-          piece_prev(dxc * 3 + dy);
+          if constexpr (decltype(with_pieces)::value) piece_prev(dxc * 3 + dy);
 #pragma unroll
           for (int j = 0; j < NJW; ++j) afc[j] = afn[j];
           if (C::SPLIT) {
@@ -618,7 +636,14 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
             for (int j = 0; j < NJW; ++j) alc[j] = aln[j];
           }
         }
-      }
+      };
+      // the first PEEL steps (unrolled: their piece indices are constants) carry
+      // the previous tile's epilogue pieces; the rest run as a plain loop
+      constexpr int PEEL = PIPE ? ((NPIECE + 2) / 3 < 3 * C::CPT ? (NPIECE + 2) / 3 : 3 * C::CPT) : 0;
+#pragma unroll
+      for (int dxc = 0; dxc < PEEL; ++dxc) dxc_step(dxc, std::true_type{});
+#pragma unroll C::RUNROLL
+      for (int dxc = PEEL; dxc < 3 * C::CPT; ++dxc) dxc_step(dxc, std::false_type{});
     } else {
 #pragma unroll C::UNROLL
       for (int ch = 0; ch < C::NCH; ++ch) {
