@@ -17,7 +17,11 @@ Two arms are timed:
             started from the learned warm start when its weights are
             available (else from y),
   fp32      fp32 matrix-core convs from x0 = y ("FP32 plain").
-Prints one JSON line (value = headline images/s).
+Inside the timed region one launch in five of each 64->64 conv class carries
+HIP events (its device time feeds the roofline figures).  After it: one solve
+with every kernel class timed, the tanh-blur workload (16x3x128x128, fp32), the
+4x3x512x512 batch from y, zero and the warm start, and the float64 oracle on
+the host.  Prints one JSON line (value = headline images/s).
 """
 import argparse
 import json
@@ -78,15 +82,16 @@ def make_problem(torch, n=8, h=256, w=256):
     return ctx, y.contiguous(), layers, taps, xt, nz
 
 
-def time_arm(torch, ctx, y, K, W, profile=None, **kw):
+def time_arm(torch, ctx, y, K, W, profile=None, every=1, check=True, **kw):
     """W warm-up solves, then K timed solves; ``profile``: names of the kernel
-    classes whose launches are timed by HIP events inside the timed region."""
+    classes whose launches are timed by HIP events inside the timed region, one
+    launch in ``every`` of each class."""
     for _ in range(W):
         ctx.solve(y, **kw)
     torch.cuda.synchronize()
     if profile:
-        ctx.profile(True, classes=profile)
-    times, iters, low, mid = [], [], [], []
+        ctx.profile(True, classes=profile, every=every)
+    times, iters, low, mid, status = [], [], [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(K):
@@ -97,13 +102,62 @@ def time_arm(torch, ctx, y, K, W, profile=None, **kw):
         iters.append(res.iters.tolist())
         low.append(res.iters_low.tolist())
         mid.append(res.iters_mid.tolist())
-        assert (res.status == 0).all(), f"solve did not converge: {res.status}"
+        status.append(res.status.tolist())
+        assert not check or (res.status == 0).all(), f"solve did not converge: {res.status}"
     total = time.perf_counter() - t_all
     prof = ctx.profile_read() if profile else None
     if profile:
         ctx.profile(False)
     return dict(total_s=total, step_s=times, iters=iters, iters_low=low, iters_mid=mid, prof=prof,
-                x=x)
+                x=x, status=status)
+
+
+def also_measured(torch, poll, ws):
+    """The other workloads the headline's measurement plan names, timed briefly
+    (1 warm-up + 2 timed solves each): the tanh-blur problem in fp32 and the
+    4 x 3 x 512 x 512 deblurring batch from y, zero and the warm start."""
+    import synth
+    from paper_2605_19705_amd import IDQ
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def batch(ctx, cfg_id, n, h, w):
+        xt, nz = synth.make_batch(cfg_id, n, 3, h, w)
+        y = ctx.apply_A(torch.from_numpy(xt).float().to(dev)) + \
+            0.01 * torch.from_numpy(nz).float().to(dev)
+        y = y.contiguous()
+        v0 = torch.from_numpy(synth.random_field(12345, tuple(y.shape))).float().to(dev)
+        return y, 0.9 / ctx.lipschitz(y, y, v0, lam=1.0, iters=30, conv_prec="f32")
+
+    def summary(r, n):
+        return {"images_per_s": n * len(r["step_s"]) / r["total_s"],
+                "ms_per_solve": 1e3 * r["total_s"] / len(r["step_s"]),
+                "iters_per_image": r["iters"][-1], "status": r["status"][-1]}
+
+    log("bench: tanh-blur workload (16x3x128x128, fp32)")
+    ctx3 = IDQ(synth.he_normal_net(synth.net_channels("gray16"), 0), op_kind="tanh_blur",
+               taps=synth.uniform_taps(7), device=0)
+    y3, tau3 = batch(ctx3, 3, 16, 128, 128)
+    r = time_arm(torch, ctx3, y3, 2, 1, check=False, conv_prec="f32", beta=0.5, tau=tau3,
+                 lam=1.0, tol=1e-4, max_iter=2000, poll_every=poll)
+    out["tanh_blur_16x3x128_fp32"] = dict(
+        summary(r, 16), workload="A(x) = tanh(2 k*x) / tanh 2, 7x7 uniform k, noise 0.01, "
+                                 "1->16->16->1 softplus net per channel, fp32 convs")
+    del ctx3, y3
+
+    log("bench: 4x3x512x512 deblurring from y, zero and the warm start")
+    ctx5 = IDQ(synth.he_normal_net(synth.net_channels("rgb64"), 0), op_kind="blur",
+               taps=synth.gaussian_taps(9, 1.6), device=0)
+    y5, tau5 = batch(ctx5, 5, 4, 512, 512)
+    kw = dict(beta=0.5, tau=tau5, lam=1.0, tol=1e-4, max_iter=3000, poll_every=poll,
+              conv_prec="bf16", refine_prec="bf16x3", switch_tol=2e-3, switch_patience=5)
+    res5 = {}
+    for init in ("y", "zero") + (("warmstart",) if ws is not None else ()):
+        extra = dict(ws=ws, ws_prec="bf16") if init == "warmstart" else {}
+        res5[init] = summary(time_arm(torch, ctx5, y5, 2, 1, check=False, init=init, **kw,
+                                      **extra), 4)
+    out["deblur_4x3x512_by_init"] = res5
+    return out
 
 
 def class_breakdown(torch, ctx, y, **kw):
@@ -163,6 +217,11 @@ def main():
                     help="solver iterations enqueued between host polls of the phases")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel class inside the timed region (slower)")
+    ap.add_argument("--sample-every", type=int, default=5,
+                    help="time one launch in this many of each timed class inside the timed "
+                         "region (each timed launch holds the queue for its event packets)")
+    ap.add_argument("--no-also", action="store_true",
+                    help="skip the tanh-blur and 512^2 warm-start measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB device-to-device (a plain copy "
                          "kernel of known size, for scaling hardware byte counters)")
@@ -214,7 +273,7 @@ def main():
         f"{args.warmup} warmup + {args.steps} timed solves")
     head = time_arm(torch, ctx, y, args.steps, args.warmup,
                     profile=PROF_CLASSES if args.profile_all else ["conv64_bf16", "conv64_bf16x3"],
-                    **head_kw)
+                    every=args.sample_every, **head_kw)
     n_img = y.shape[0]
     value = n_img * args.steps / head["total_s"]
     log(f"bench: headline {value:.2f} images/s, iterations {head['iters'][-1]}, "
@@ -250,13 +309,16 @@ def main():
                 "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": per_px * px / launches,
                 "kernel": "conv_mfma_kernel<%s, 64, 64>" % ("bf16x3" if split else "bf16"),
-                "launches": launches, "avg_launch_us": avg_ms * 1e3,
+                "launches": launches, "sampled_every": args.sample_every,
+                "avg_launch_us": avg_ms * 1e3,
                 "total_ms": ms, "flop_per_launch": flops_per_launch}
     rl = {c: conv_roofline(c) for c in ("conv64_bf16x3", "conv64_bf16")}
     order = sorted((r for r in rl.values() if r), key=lambda r: -r["total_ms"])
     roofline = order[0]
     roofline_other = order[1] if len(order) > 1 else None
     phases = class_breakdown(torch, ctx, y, **head_kw)
+
+    also = None if args.no_also else also_measured(torch, args.poll, ws)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -297,6 +359,7 @@ def main():
         "device_ms_by_class_one_solve": phases,
         "roofline": roofline,
         "roofline_other": roofline_other,
+        "also_measured": also,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

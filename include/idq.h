@@ -244,6 +244,14 @@ int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_d
  * Synchronous. */
 #define IDQ_PROF_ALL 0x7fffffff
 int idq_profile_enable(idq_ctx* ctx, int on);
+/* Time only one launch in `every` (>= 1; default 1) of each timed class: the
+ * first launch after the enable and then every `every`-th, counted per class.
+ * The read-out then covers the sampled launches only (an average per launch
+ * stays unbiased when `every` is coprime with the launch pattern), and the
+ * event packets, which hold the queue a few microseconds each, cost 1/`every`
+ * as much.  Restarts the per-class launch count; kept across enables.
+ * IDQ_E_INVAL for every < 1. */
+int idq_profile_sample(idq_ctx* ctx, int every);
 /* Totals since the last enable: summed device time (ms), number of launches
  * and output pixels computed (conv classes; 0 otherwise).  Synchronous. */
 int idq_profile_read(idq_ctx* ctx, int cls, double* total_ms, long long* launches,

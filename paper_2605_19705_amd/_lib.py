@@ -29,7 +29,7 @@ EXPORTED = [
     "idq_last_error", "idq_version", "idq_solve_opts_default", "idq_create", "idq_destroy",
     "idq_set_params", "idq_num_params", "idq_apply_A", "idq_apply_AT", "idq_grad_data",
     "idq_grad_reg", "idq_hvp", "idq_lipschitz", "idq_solve", "idq_backward",
-    "idq_profile_enable", "idq_profile_read",
+    "idq_profile_enable", "idq_profile_sample", "idq_profile_read",
     "idq_ws_create", "idq_ws_destroy", "idq_ws_num_params", "idq_ws_get_params",
     "idq_ws_set_params", "idq_ws_forward", "idq_ws_train_step", "idq_ws_grad",
 ]
@@ -94,6 +94,7 @@ _SIGS = {
     "idq_backward": ([vp, vp, vp, vp, vp, dp, ip, ip, ip, ip, ip, C.POINTER(BwdOpts),
                       C.POINTER(BwdInfo), vp], ip),
     "idq_profile_enable": ([vp, ip], ip),
+    "idq_profile_sample": ([vp, ip], ip),
     "idq_profile_read": ([vp, ip, dp, C.POINTER(C.c_longlong), dp], ip),
     "idq_ws_create": ([C.POINTER(vp), dp, C.c_longlong, ip], ip),
     "idq_ws_destroy": ([vp], ip),

@@ -126,9 +126,10 @@ class IDQ:
                                        flat.size))
 
     # ---- device-time accounting ---------------------------------------------------
-    def profile(self, on=True, classes=None):
+    def profile(self, on=True, classes=None, every=1):
         """Time device work per class; ``classes``: names of L.PROF_CLASSES to time
-        (all when None)."""
+        (all when None); ``every``: time one launch in that many of each class."""
+        L.check(L.lib().idq_profile_sample(self._h, int(every)))
         mask = 0
         if on:
             mask = L.IDQ_PROF_ALL if classes is None else sum(1 << L.PROF_CLASSES[c] for c in classes)

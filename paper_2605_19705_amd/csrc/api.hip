@@ -55,7 +55,10 @@ int Profiler::take(int cls, ProfRec* r) {
       *e = pool.back();
       pool.pop_back();
     } else {
-      IDQ_HIP(hipEventCreate(e));
+      // timing only: the elapsed times are read after the stream has been
+      // synchronized, so the events need no system-scope fence (which would
+      // write back and invalidate the caches around every timed launch)
+      IDQ_HIP(hipEventCreateWithFlags(e, hipEventDisableSystemFence));
     }
   }
   return IDQ_OK;
@@ -111,7 +114,7 @@ int run_conv(idq_ctx* ctx, ConvArgs a, int prec, hipStream_t s) {
   if (a.CI == 64 && a.CO == 64 && prec != PREC_F64)
     cls = prec == PREC_BF16 ? PC_CONV_WIDE_BF16
                             : (prec == PREC_SPLIT ? PC_CONV_WIDE_SPLIT : PC_CONV_WIDE_F32);
-  if (!ctx->prof.timed(cls)) return launch_conv(a, prec, s);
+  if (!ctx->prof.sample(cls)) return launch_conv(a, prec, s);
   a.work_px = ctx->prof.dev_px + cls;
   // the launcher stamps the events from the dispatch itself (hipExtLaunchKernel)
   // so that they time the kernel alone, not its launch latency
@@ -126,7 +129,7 @@ int run_conv(idq_ctx* ctx, ConvArgs a, int prec, hipStream_t s) {
 
 template <class F>
 int profiled(idq_ctx* ctx, int cls, hipStream_t s, F&& f) {
-  if (!ctx->prof.timed(cls)) return f();
+  if (!ctx->prof.sample(cls)) return f();
   ProfRec r;
   IDQ_TRY(ctx->prof.begin(cls, s, &r));
   IDQ_TRY(f());
@@ -1021,9 +1024,19 @@ int idq_profile_enable(idq_ctx* ctx, int on) {
     for (int i = 0; i < PC_COUNT; ++i) {
       ctx->prof.ms[i] = 0.0;
       ctx->prof.launches[i] = 0;
+      ctx->prof.seen[i] = 0;
     }
     ctx->prof.on = on != 0;
     ctx->prof.mask = static_cast<unsigned>(on);
+    return IDQ_OK;
+  });
+}
+
+int idq_profile_sample(idq_ctx* ctx, int every) {
+  return guarded([&]() -> int {
+    if (!ctx || every < 1) return fail(IDQ_E_INVAL, "profile sampling needs every >= 1");
+    ctx->prof.every = every;
+    for (int i = 0; i < PC_COUNT; ++i) ctx->prof.seen[i] = 0;
     return IDQ_OK;
   });
 }

@@ -50,6 +50,9 @@ struct Profiler {
   bool on = false;
   unsigned mask = 0;   // classes timed while on (bit cls)
   bool timed(int cls) const { return on && ((mask >> cls) & 1u); }
+  int every = 1;                   // time one launch in `every` of each class
+  long long seen[PC_COUNT] = {};   // launches of each class since the enable
+  bool sample(int cls) { return timed(cls) && (seen[cls]++ % every) == 0; }
   std::vector<hipEvent_t> pool;
   std::vector<ProfRec> pending;
   double ms[PC_COUNT] = {};
