@@ -5,6 +5,8 @@
 //   * conv_direct: one thread per (pixel, 16 output channels), scalar FMA in the
 //     math type.  Used for float64 and for shapes the MFMA kernels do not cover.
 //   * conv_mfma (k_conv_mfma.hip): implicit GEMM on the gfx950 matrix cores.
+//   * conv_thin (k_conv_thin.hip): image-facing outputs (CO <= 3) from NHWC
+//     activations, float32 on the vector ALUs.
 // Every pass is   acc[co](p) = sum_{ci, tap} W[co][ci][tap] * a[ci](p + off(tap))
 // with the operand a produced by the prologue (Pro) and the result consumed by
 // the epilogue (Epi); see kernels.h.
@@ -149,6 +151,7 @@ int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
       return fail(IDQ_E_UNSUPPORTED, "split-bf16 conv pass of an unsupported form");
     return launch_conv_mfma(a, prec, s);
   }
+  if (!force_direct() && thin_supported(a, prec)) return launch_conv_thin(a, prec, s);
   if (prec != PREC_F64 && a.wmfma && !force_direct() && mfma_supported(prec, a.CI, a.CO) &&
       mfma_form_ok(a, prec))
     return launch_conv_mfma(a, prec, s);

@@ -66,20 +66,23 @@ struct Cfg {
   static constexpr int LO_OFF = CIP * ES;
   static constexpr int PIXB = (SPLIT ? 2 : 1) * CIP * ES + (VEC ? 16 : 0);
   static constexpr int LDS_IN = (NPIX * PIXB + 15) / 16 * 16;
-  // launch shape: 4 waves of 4 output rows, one workgroup per tile; the split
-  // 64 -> 64 passes instead run 8 waves of 2 rows (two waves per SIMD, so one
-  // wave's matrix-core work overlaps the other's staging and epilogue) and give
-  // each of two workgroups per tile half of the output channels, so that both
-  // the hi and the lo weight fragments of that half fit in LDS beside the tile
-  static constexpr bool WIDE8 = SPLIT && CI == 64 && CO == 64;
-  static constexpr int WAVES = WIDE8 ? 8 : 4;
+  // launch shape: 4 waves of 4 output rows, one workgroup per tile.  Split
+  // passes over 64 input channels run 8 waves of 2 rows instead (two waves per
+  // SIMD, so one wave's matrix-core work overlaps the other's staging and
+  // epilogue); with 64 output channels, two workgroups per tile each take half
+  // of them, so that both the hi and the lo weight fragments of that half fit
+  // in LDS beside the tile
+  static constexpr bool W8 = SPLIT && CI == 64;
+  static constexpr int WAVES = W8 ? 8 : 4;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int RWV = TH / WAVES;         // output rows per wave
-  static constexpr int CSPLIT = WIDE8 ? 2 : 1;   // workgroups (channel groups) per tile
+  static constexpr int CSPLIT = (W8 && CO == 64) ? 2 : 1;  // workgroups per tile
   static constexpr int NJW = NJ / CSPLIT;        // 16-channel blocks per workgroup
   static constexpr bool WLDS = MBF;              // hi (bf16, split) fragments in LDS
-  static constexpr bool WLO_LDS = WIDE8;         // split lo fragments in LDS too (else L2)
   static constexpr int WBYTES = NCH * NJW * 64 * 16;
+  // split lo fragments in LDS too where they fit, else read from L2 (where a
+  // wait for one also waits for the next tile's halo loads issued before it)
+  static constexpr bool WLO_LDS = SPLIT && LDS_IN + 2 * WBYTES <= 160 * 1024;
   static constexpr int LDS = LDS_IN + (WLDS ? WBYTES * (WLO_LDS ? 2 : 1) : 0);
   // prefetch: 16-byte items (VEC) or floats (gather) per thread for one tile
   static constexpr int VPP = VEC ? CI / GV : 0;
@@ -780,8 +783,8 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
   X(1, 16) X(16, 16) X(3, 64) X(64, 64) X(3, 32) X(32, 32) X(32, 64) X(64, 32) X(96, 32) X(32, 96)
 #define IDQ_MFMA_THIN(X) X(16, 1) X(64, 3) X(32, 3)
 // split (hi/lo bf16) instantiations: the channel counts that are whole K chunks
+// (image-facing outputs run in float32 on the vector ALUs, k_conv_thin.hip)
 #define IDQ_MFMA_SPLIT(X) X(64, 64) X(32, 32) X(32, 64) X(64, 32)
-#define IDQ_MFMA_SPLIT_THIN(X) X(64, 3) X(32, 3)
 
 }  // namespace mfma
 }  // namespace idq

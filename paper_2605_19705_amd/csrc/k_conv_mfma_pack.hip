@@ -13,7 +13,6 @@ bool mfma_supported(int prec, int ci, int co) {
   if (prec == PREC_SPLIT) {
 #define X(A, B) if (ci == A && co == B) return true;
     IDQ_MFMA_SPLIT(X)
-    IDQ_MFMA_SPLIT_THIN(X)
 #undef X
     return false;
   }

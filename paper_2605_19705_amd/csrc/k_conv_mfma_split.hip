@@ -17,13 +17,6 @@ int by_epi(const ConvArgs& a, hipStream_t s) {
   }
 }
 
-template <int CI, int CO>
-int thin(const ConvArgs& a, hipStream_t s) {
-  if (a.epi == E_RES) return launch_shape<PREC_SPLIT, CI, CO, P_NONE, E_RES>(a, s);
-  if (a.epi == E_SUB) return launch_shape<PREC_SPLIT, CI, CO, P_NONE, E_SUB>(a, s);
-  return fail(IDQ_E_UNSUPPORTED, "no split-bf16 MFMA epilogue of this kind");
-}
-
 }  // namespace
 
 int launch_split(const ConvArgs& a, hipStream_t s) {
@@ -31,10 +24,6 @@ int launch_split(const ConvArgs& a, hipStream_t s) {
 #define X(A, B) \
   if (a.CI == A && a.CO == B) return by_epi<A, B>(a, s);
   IDQ_MFMA_SPLIT(X)
-#undef X
-#define X(A, B) \
-  if (a.CI == A && a.CO == B) return thin<A, B>(a, s);
-  IDQ_MFMA_SPLIT_THIN(X)
 #undef X
   return fail(IDQ_E_UNSUPPORTED, "no split-bf16 MFMA instantiation for this shape");
 }

@@ -88,6 +88,9 @@ int launch_conv(const ConvArgs& a, int prec, hipStream_t s);
 size_t pack_mfma_weights(int prec, int ci, int co, const double* w /*[co][ci][9]*/,
                          void* dst_host);
 bool mfma_supported(int prec, int ci, int co);
+// float32 vector-ALU kernel for image-facing outputs (k_conv_thin.hip)
+bool thin_supported(const ConvArgs& a, int prec);
+int launch_conv_thin(const ConvArgs& a, int prec, hipStream_t s);
 
 // ---- stencils of the forward operator (circular, per plane) --------------
 enum StencilMode {
