@@ -464,11 +464,25 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
   // the first tile's halo is requested before the weights, and the weight
   // fragments are fetched in batches of WB loads per thread before any is
   // written to LDS, so the L2 round trips of the prologue overlap
-  Prefetch<C, PRO> pf;
-  {
-    const int ni = t / tiles_per_img, rem = t - ni * tiles_per_img;
-    load_tile<C, CI, PRO>(a, pf, ni, (rem / ntx) * TH, (rem % ntx) * TW, tid);
-  }
+  auto next_open = [&](int tt) {
+    tt += tstep;
+    while (tt < ntiles && !open(tt)) tt += tstep;
+    return tt;
+  };
+  auto issue = [&](Prefetch<C, PRO>& p, int tt) {
+    if (tt < ntiles) {
+      const int ni = tt / tiles_per_img, rem = tt - ni * tiles_per_img;
+      load_tile<C, CI, PRO>(a, p, ni, (rem / ntx) * TH, (rem % ntx) * TW, tid);
+    }
+  };
+  // halos in registers ahead of the LDS stage: one tile, or two for the 8-wave
+  // split shape (whose matrix-core work per tile is short next to the HBM
+  // latency of the next halo; the second buffer fits its register budget)
+  constexpr int DEPTH = C::W8 ? 2 : 1;
+  Prefetch<C, PRO> pf, pf2;
+  int t1 = DEPTH > 1 ? next_open(t) : 0;
+  issue(pf, t);
+  if (DEPTH > 1) issue(pf2, t1);
   if (C::WLDS) {
     // LDS fragment i = (ch * NJW + jj) * 64 + lane of this workgroup's channel
     // blocks; the lo parts (WLO_LDS) follow the hi parts
@@ -526,19 +540,16 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
     }
   };
 
-  while (t < ntiles) {
+  // one tile: stage its halo from `pcur` into LDS, refill `pcur` with the halo
+  // of tile `tfill` (DEPTH tiles ahead), then the K loop and the epilogue
+  auto tile = [&](Prefetch<C, PRO>& pcur, const int t, const int tfill) {
     const int ni = t / tiles_per_img;
     const int rem = t - ni * tiles_per_img;
     const int ty0 = (rem / ntx) * TH, tx0 = (rem % ntx) * TW;
     __syncthreads();  // the previous tile's fragments have been read
-    store_tile<C, CI, PRO>(a, pf, lin, tid);
+    store_tile<C, CI, PRO>(a, pcur, lin, tid);
     __syncthreads();
-    int tn = t + tstep;
-    while (tn < ntiles && !open(tn)) tn += tstep;
-    if (tn < ntiles) {
-      const int nn = tn / tiles_per_img, rn = tn - nn * tiles_per_img;
-      load_tile<C, CI, PRO>(a, pf, nn, (rn / ntx) * TH, (rn % ntx) * TW, tid);
-    }
+    issue(pcur, tfill);
     if (a.work_px && tid == 0 && jh == 0) {
       const int vh = a.H - ty0 < TH ? a.H - ty0 : TH, vw = a.W - tx0 < TW ? a.W - tx0 : TW;
       atomicAdd(a.work_px, static_cast<unsigned long long>(vh * vw));
@@ -724,7 +735,28 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
           epilogue_piece<C, CO, EPI>(a, acc[r][j], ep.v[r][j], bias_r[j], ni, ty0, tx0, wv, r,
                                      jh * NJW + j, g, c16, sp);
     }
-    t = tn;
+  };
+
+  if constexpr (DEPTH == 1) {
+    while (t < ntiles) {
+      const int tn = next_open(t);
+      tile(pf, t, tn);
+      t = tn;
+    }
+  } else {
+    // tiles alternate between the two buffers: t staged from pf (refilled with
+    // the tile after t1), t1 from pf2
+    while (t < ntiles) {
+      int t2 = next_open(t1);
+      tile(pf, t, t2);
+      t = t1;
+      t1 = t2;
+      if (t >= ntiles) break;
+      t2 = next_open(t1);
+      tile(pf2, t, t2);
+      t = t1;
+      t1 = t2;
+    }
   }
   if constexpr (PIPE) {
 #pragma unroll
