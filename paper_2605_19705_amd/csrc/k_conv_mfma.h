@@ -72,14 +72,17 @@ struct Cfg {
   // epilogue); with 64 output channels, two workgroups per tile each take half
   // of them, so that both the hi and the lo weight fragments of that half fit
   // in LDS beside the tile
-  static constexpr bool W8 = SPLIT && CI == 64;
+  static constexpr bool W8 = (SPLIT && CI == 64) || (PREC == PREC_F32 && CI <= 4 && CO == 64);
   static constexpr int WAVES = W8 ? 8 : 4;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int RWV = TH / WAVES;         // output rows per wave
-  static constexpr int CSPLIT = (W8 && CO == 64) ? 2 : 1;  // workgroups per tile
+  static constexpr int CSPLIT = (SPLIT && CI == 64 && CO == 64) ? 2 : 1;  // workgroups per tile
   static constexpr int NJW = NJ / CSPLIT;        // 16-channel blocks per workgroup
-  static constexpr bool WLDS = MBF;              // hi (bf16, split) fragments in LDS
   static constexpr int WBYTES = NCH * NJW * 64 * 16;
+  // weight fragments in LDS: always for bf16 operands (hi parts for split);
+  // float32 ones where they are small (else they come from L2, where a wait
+  // for one also waits for the halo and epilogue loads issued before it)
+  static constexpr bool WLDS = MBF || WBYTES <= 48 * 1024;
   // split lo fragments in LDS too where they fit, else read from L2 (where a
   // wait for one also waits for the next tile's halo loads issued before it)
   static constexpr bool WLO_LDS = SPLIT && LDS_IN + 2 * WBYTES <= 160 * 1024;

@@ -2,6 +2,9 @@
 // forward operator, the inertial extrapolation, the fused update with its
 // float64 residual partial sums, the per-image finalize step (stopping rule,
 // restart, precision phase) and deterministic float64 reductions.
+#include <cstdint>
+#include <initializer_list>
+
 #include "kernels.h"
 
 namespace idq {
@@ -296,18 +299,127 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a) {
   }
 }
 
-__global__ void finalize_kernel(FinalizeArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+// float32 images of a multiple of 4 elements: 16-byte accesses, each thread
+// issuing the loads of kU vectors before using any (the scalar loop above
+// waits for every element's loads in turn)
+constexpr int kU = 4;
+
+__global__ __launch_bounds__(kBlock) void extrap_f4_kernel(const float4* x, const float4* xp,
+                                                         float4* z, const double* beta_eff,
+                                                         const int* gate, long long per4) {
+  const int img = blockIdx.y;
+  if (gate && gate[img] == G_DONE) return;
+  const float b = static_cast<float>(beta_eff[img]);
+  const size_t base = static_cast<size_t>(img) * per4;
+  const long long step = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i0 = blockIdx.x * static_cast<long long>(kBlock) + threadIdx.x; i0 < per4;
+       i0 += step * kU) {
+    float4 xv[kU], pv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * step;
+      if (i < per4) {
+        xv[u] = x[base + i];
+        pv[u] = xp[base + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * step;
+      if (i < per4)
+        z[base + i] = make_float4(xv[u].x + b * (xv[u].x - pv[u].x), xv[u].y + b * (xv[u].y - pv[u].y),
+                                  xv[u].z + b * (xv[u].z - pv[u].z), xv[u].w + b * (xv[u].w - pv[u].w));
+    }
+  }
+}
+
+__device__ inline void upd1(float x, float z, float g, float q, float tau, float lam, float& out,
+                            double& s1, double& s0, double& nf) {
+  const float v = z - tau * (g + lam * q);
+  out = v;
+  const double d = static_cast<double>(v) - static_cast<double>(x);
+  s1 += d * d;
+  s0 += static_cast<double>(x) * static_cast<double>(x);
+  if (!isfinite(v)) nf += 1.0;
+}
+
+__global__ __launch_bounds__(kBlock) void update_f4_kernel(UpdateArgs a) {
+  const int img = blockIdx.y;
+  const int blk = blockIdx.x;
+  if (a.gate && a.gate[img] == G_DONE) return;
+  const long long per4 = a.per / 4;
+  const size_t base = static_cast<size_t>(img) * per4;
+  const long long chunk = (per4 + a.nblk - 1) / a.nblk;
+  const long long lo = blk * chunk;
+  const long long hi = lo + chunk < per4 ? lo + chunk : per4;
+  const float4* x = static_cast<const float4*>(a.x) + base;
+  const float4* z = static_cast<const float4*>(a.z) + base;
+  const float4* gf = a.gf ? static_cast<const float4*>(a.gf) + base : nullptr;
+  const float4* p = a.p ? static_cast<const float4*>(a.p) + base : nullptr;
+  const float4* y = a.y ? static_cast<const float4*>(a.y) + base : nullptr;
+  const float4* q = a.q ? static_cast<const float4*>(a.q) + base : nullptr;
+  float4* xn = static_cast<float4*>(a.xn) + base;
+  const float tau = static_cast<float>(a.tau), lam = static_cast<float>(a.lambda);
+  double s1 = 0.0, s0 = 0.0, nf = 0.0;
+  for (long long i0 = lo + threadIdx.x; i0 < hi; i0 += kBlock * kU) {
+    float4 xv[kU], zv[kU], gv[kU], qv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * kBlock;
+      if (i < hi) {
+        xv[u] = x[i];
+        zv[u] = z[i];
+        if (gf) {
+          gv[u] = gf[i];
+        } else {
+          const float4 pv = p[i], yv = y[i];
+          gv[u] = make_float4(pv.x - yv.x, pv.y - yv.y, pv.z - yv.z, pv.w - yv.w);
+        }
+        qv[u] = q ? q[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * kBlock;
+      if (i < hi) {
+        float4 o;
+        upd1(xv[u].x, zv[u].x, gv[u].x, qv[u].x, tau, lam, o.x, s1, s0, nf);
+        upd1(xv[u].y, zv[u].y, gv[u].y, qv[u].y, tau, lam, o.y, s1, s0, nf);
+        upd1(xv[u].z, zv[u].z, gv[u].z, qv[u].z, tau, lam, o.z, s1, s0, nf);
+        upd1(xv[u].w, zv[u].w, gv[u].w, qv[u].w, tau, lam, o.w, s1, s0, nf);
+        xn[i] = o;
+      }
+    }
+  }
+  block_sum3(s1, s0, nf);
+  if (threadIdx.x == 0) {
+    double* o = a.partials + (static_cast<size_t>(img) * a.nblk + blk) * 3;
+    o[0] = s1;
+    o[1] = s0;
+    o[2] = nf;
+  }
+}
+
+// One wave per image: its lanes sum the update's block partials in a fixed
+// order (strided, then a shuffle tree), lane 0 applies the rules.
+__global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
   ImgState s = a.st[i];
   if (s.done) return;
   double s1 = 0.0, s0 = 0.0, nf = 0.0;
   const double* p = a.partials + static_cast<size_t>(i) * a.nblk * 3;
-  for (int b = 0; b < a.nblk; ++b) {
+  for (int b = lane; b < a.nblk; b += 64) {
     s1 += p[3 * b];
     s0 += p[3 * b + 1];
     nf += p[3 * b + 2];
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, 64);
+    s0 += __shfl_down(s0, off, 64);
+    nf += __shfl_down(nf, off, 64);
+  }
+  if (lane != 0) return;
   s.it += 1;
   s.kr += 1;
   s.S += s1;
@@ -504,6 +616,14 @@ __global__ __launch_bounds__(kBlock) void reduce_chunks_kernel(const double* par
   out[i] = accumulate ? static_cast<T>(static_cast<double>(out[i]) + v) : static_cast<T>(v);
 }
 
+// 16-byte vector access needs every image to start 16-byte aligned
+inline bool vec4_ok(long long per, std::initializer_list<const void*> ptrs) {
+  if (per % 4 != 0) return false;
+  for (const void* p : ptrs)
+    if (p && (reinterpret_cast<uintptr_t>(p) & 15u) != 0) return false;
+  return true;
+}
+
 inline int grid_for(long long per) {
   long long g = (per + kBlock - 1) / kBlock;
   if (g > 1024) g = 1024;
@@ -523,6 +643,16 @@ int launch_stencil(const StencilArgs& a, const double* taps_host, int dtype, hip
 
 int launch_extrap(const void* x, const void* xp, void* z, const double* beta_eff,
                   const int* gate, int n, long long per, int dtype, hipStream_t s) {
+  if (dtype == IDQ_F32 && vec4_ok(per, {x, xp, z})) {
+    const long long per4 = per / 4;
+    long long g = (per4 + kBlock * kU - 1) / (kBlock * kU);
+    dim3 grid(static_cast<int>(g < 1 ? 1 : (g > 256 ? 256 : g)), n);
+    extrap_f4_kernel<<<grid, kBlock, 0, s>>>(static_cast<const float4*>(x),
+                                             static_cast<const float4*>(xp),
+                                             static_cast<float4*>(z), beta_eff, gate, per4);
+    IDQ_HIP(hipGetLastError());
+    return IDQ_OK;
+  }
   dim3 grid(grid_for(per), n);
   if (dtype == IDQ_F64)
     extrap_kernel<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(x),
@@ -540,6 +670,8 @@ int launch_update(const UpdateArgs& a, int dtype, hipStream_t s) {
   dim3 grid(a.nblk, a.n);
   if (dtype == IDQ_F64)
     update_kernel<double><<<grid, kBlock, 0, s>>>(a);
+  else if (vec4_ok(a.per, {a.x, a.z, a.gf, a.p, a.y, a.q, a.xn}))
+    update_f4_kernel<<<grid, kBlock, 0, s>>>(a);
   else
     update_kernel<float><<<grid, kBlock, 0, s>>>(a);
   IDQ_HIP(hipGetLastError());
@@ -547,7 +679,7 @@ int launch_update(const UpdateArgs& a, int dtype, hipStream_t s) {
 }
 
 int launch_finalize(const FinalizeArgs& a, hipStream_t s) {
-  finalize_kernel<<<(a.n + 63) / 64, 64, 0, s>>>(a);
+  finalize_kernel<<<a.n, 64, 0, s>>>(a);
   IDQ_HIP(hipGetLastError());
   return IDQ_OK;
 }
