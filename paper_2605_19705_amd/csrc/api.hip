@@ -459,6 +459,7 @@ StencilArgs stencil_base(const idq_ctx* ctx, const Geometry& g, const int* gate)
   a.kw = ctx->kw;
   a.gain = ctx->gain;
   a.gate = gate;
+  a.gate_mask = GM_ACTIVE;
   a.plane_div = g.c;
   return a;
 }
@@ -471,7 +472,7 @@ int copy_state(const void* src, void* dst, size_t bytes, hipStream_t s) {
 // grad f(p, y) = J_A(p)^T (A(p) - y) into gf (not used for the identity,
 // whose gradient p - y the update kernel forms itself unless `force`).
 int data_grad(idq_ctx* ctx, const Geometry& g, int dtype, const void* p, const void* y, void* gf,
-              const int* gate, hipStream_t s, bool force) {
+              const int* gate, hipStream_t s, bool force, int mask = GM_ACTIVE) {
   const size_t sbytes = static_cast<size_t>(g.n) * g.per * elem_size(dtype);
   if (ctx->op_kind == IDQ_OP_IDENTITY) {
     if (force) IDQ_TRY(launch_axpbypcz(1.0, p, -1.0, y, 0.0, nullptr, gf, g.n * g.per, dtype, s));
@@ -480,12 +481,14 @@ int data_grad(idq_ctx* ctx, const Geometry& g, int dtype, const void* p, const v
   void* tmp;
   IDQ_TRY(ctx->ws.get(W_S, sbytes, &tmp));
   StencilArgs a = stencil_base(ctx, g, gate);
+  a.gate_mask = mask;
   a.in0 = p;
   a.aux = y;
   a.out = tmp;
   a.mode = ctx->op_kind == IDQ_OP_BLUR_CIRC ? S_B_MINUS : S_TANH_WRES;
   IDQ_TRY(profiled(ctx, PC_STENCIL, s, [&] { return launch_stencil(a, ctx->taps.data(), dtype, s); }));
   StencilArgs b = stencil_base(ctx, g, gate);
+  b.gate_mask = mask;
   b.in0 = tmp;
   b.out = gf;
   b.mode = S_BT;
@@ -663,7 +666,16 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   const bool bf_start = o->conv_prec == IDQ_BF16;
   const bool use_mid = bf_start && o->refine_prec == IDQ_BF16X3;
   const int final_prec = bf_start ? IDQ_F32 : o->conv_prec;
-  bool low_live = bf_start, mid_live = use_mid;
+  // Phases launched in a step, from the last poll: an image moves at most one
+  // phase per update, so the bf16 phase ends once a poll finds none in it, and
+  // the split phase cannot be reached in the first step after a poll that found
+  // none there.  The float32 phase of a bf16 start is launched only once a poll
+  // has found an image in it: one that enters it between polls waits, unchanged
+  // and uncounted, until then (each image needs about one float32 update, and
+  // an empty float32 pass per step costs more than that wait).
+  bool low_live = bf_start, mid_live = use_mid, mid_seen = false, fin_live = !bf_start;
+  // waiting steps do not count towards an image's iterations
+  const int host_limit = bf_start ? limit + 2 * poll + 2 : limit;
   const int* gp = static_cast<const int*>(gate);
   const bool identity = ctx->op_kind == IDQ_OP_IDENTITY;
 
@@ -684,21 +696,27 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   fa.use_mid = use_mid ? 1 : 0;
 
   int t = 0;
-  while (t < limit) {
-    const int t_end = std::min(limit, t + poll);
-    for (; t < t_end; ++t) {
+  while (t < host_limit) {
+    // once only float32-phase images remain (a bf16 start), each needs about one
+    // more update: poll after every step rather than launch empty steps
+    const bool fin_only = bf_start && fin_live && !low_live && !mid_live;
+    const int t_end = std::min(host_limit, t + (fin_only ? 1 : poll));
+    for (int j = 0; t < t_end; ++t, ++j) {
+      const bool mid_now = mid_live && (j > 0 || mid_seen);
+      const int run = (low_live ? 1 << G_LOW : 0) | (mid_now ? 1 << G_MID : 0) |
+                      (fin_live ? 1 << G_FINAL : 0);
       void* xa = xb[t % 2];
       void* xp = xb[(t + 1) % 2];
       IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
-        return launch_extrap(xa, xp, z, static_cast<const double*>(beta), gp, n, g.per, dtype, s);
+        return launch_extrap(xa, xp, z, static_cast<const double*>(beta), gp, run, n, g.per,
+                             dtype, s);
       }));
       const void* p = o->grad_at == IDQ_GRAD_AT_CURRENT ? xa : z;
-      if (!identity) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false));
+      if (!identity) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false, run));
       if (use_net) {
-        // phases only advance, so a phase absent at the last poll stays absent
         if (low_live) IDQ_TRY(net_grad(ctx, g, IDQ_BF16, p, q, gp, 1 << G_LOW, s));
-        if (mid_live) IDQ_TRY(net_grad(ctx, g, IDQ_BF16X3, p, q, gp, 1 << G_MID, s));
-        IDQ_TRY(net_grad(ctx, g, final_prec, p, q, gp, 1 << G_FINAL, s));
+        if (mid_now) IDQ_TRY(net_grad(ctx, g, IDQ_BF16X3, p, q, gp, 1 << G_MID, s));
+        if (fin_live) IDQ_TRY(net_grad(ctx, g, final_prec, p, q, gp, 1 << G_FINAL, s));
       }
       UpdateArgs ua{};
       ua.n = n;
@@ -713,11 +731,14 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
       ua.tau = tau;
       ua.lambda = o->lambda;
       ua.gate = gp;
+      ua.run_mask = run;
       ua.partials = static_cast<double*>(part);
       ua.nblk = nblk;
       fa.buf_index = (t + 1) % 2;
-      fa.history = (hist && t < hist_len) ? static_cast<double*>(hist) : nullptr;
+      fa.history = static_cast<double*>(hist);
+      fa.history_rows = hist_len;
       fa.step = t;
+      fa.run_mask = run;
       IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
         IDQ_TRY(launch_update(ua, dtype, s));
         return launch_finalize(fa, s);
@@ -726,14 +747,17 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     IDQ_HIP(hipMemcpyAsync(ctx->host_gate, gate, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     IDQ_HIP(hipStreamSynchronize(s));
     if (ctx->prof.on) IDQ_TRY(ctx->prof.flush());
-    bool any = false, anylow = false, anymid = false;
+    bool any = false, anylow = false, anymid = false, anyfin = false;
     for (int i = 0; i < n; ++i) {
       any |= ctx->host_gate[i] != G_DONE;
       anylow |= ctx->host_gate[i] == G_LOW;
       anymid |= ctx->host_gate[i] == G_MID;
+      anyfin |= ctx->host_gate[i] == G_FINAL;
     }
     low_live = anylow;
     mid_live = use_mid && (anylow || anymid);
+    mid_seen = anymid;
+    fin_live = !bf_start || anyfin;
     if (!any) break;
   }
   IDQ_TRY(launch_gather_result(xb[0], xb[1], x_out, static_cast<const ImgState*>(state), n, g.per,

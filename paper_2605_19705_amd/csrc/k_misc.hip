@@ -54,13 +54,20 @@ __device__ inline int wrap(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
 }
+// wrap for offsets within one period of the range (the common case), without
+// the integer division
+__device__ inline int wrap1(int v, int n) {
+  if (v < 0) v += n;
+  if (v >= n) v -= n;
+  return (v < 0 || v >= n) ? wrap(v, n) : v;
+}
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs a, Taps<T> taps) {
   __shared__ T tile0[kLds];
   __shared__ T tile1[MODE == S_TANH_HESS ? kLds : 1];
   const int plane = blockIdx.z;
-  if (a.gate && a.gate[plane / a.plane_div] == G_DONE) return;
+  if (a.gate && ((1 << a.gate[plane / a.plane_div]) & a.gate_mask) == 0) return;
   const int ty0 = blockIdx.y * kTile, tx0 = blockIdx.x * kTile;
   const int ry = (a.kh - 1) / 2, rx = (a.kw - 1) / 2;
   const int LH = kTile + a.kh - 1, LW = kTile + a.kw - 1;
@@ -141,10 +148,11 @@ __device__ inline T stencil_out(T s0, T s1, T aux, T g, T tg) {
   }
 }
 
-// Square K x K taps (K odd, compile time): 16 x 32 output tiles, two
-// horizontally adjacent outputs per thread sharing their K + 1 row reads, all
+// Square K x K taps (K odd, compile time): 16 x 64 output tiles, four
+// horizontally adjacent outputs per thread sharing their K + 3 row reads, all
 // tap loops unrolled (the taps then sit in scalar registers).
-constexpr int kSTY = 16, kSTX = 32;
+constexpr int kSNO = 4;                  // outputs per thread
+constexpr int kSTY = 16, kSTX = 16 * kSNO;
 template <typename T, int MODE, int K>
 __global__ __launch_bounds__(kBlock) void stencil_k_kernel(StencilArgs a, Taps<T> taps) {
   constexpr int R = (K - 1) / 2, LH = kSTY + K - 1, LW = kSTX + K - 1;
@@ -152,39 +160,40 @@ __global__ __launch_bounds__(kBlock) void stencil_k_kernel(StencilArgs a, Taps<T
   __shared__ T tile0[LH * LW];
   __shared__ T tile1[TWO ? LH * LW : 1];
   const int plane = blockIdx.z;
-  if (a.gate && a.gate[plane / a.plane_div] == G_DONE) return;
+  if (a.gate && ((1 << a.gate[plane / a.plane_div]) & a.gate_mask) == 0) return;
   const int ty0 = blockIdx.y * kSTY, tx0 = blockIdx.x * kSTX;
   const size_t pbase = static_cast<size_t>(plane) * a.H * a.W;
   const T* in0 = static_cast<const T*>(a.in0) + pbase;
   const T* in1 = static_cast<const T*>(a.in1) + (TWO ? pbase : 0);
   for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
     const int ly = i / LW, lx = i - (i / LW) * LW;
-    const int gy = wrap(ty0 - R + ly, a.H), gx = wrap(tx0 - R + lx, a.W);
+    const int gy = wrap1(ty0 - R + ly, a.H), gx = wrap1(tx0 - R + lx, a.W);
     const size_t src = static_cast<size_t>(gy) * a.W + gx;
     tile0[i] = in0[src];
     if (TWO) tile1[i] = in1[src];
   }
   __syncthreads();
-  const int ly = threadIdx.x / (kSTX / 2), lx = (threadIdx.x % (kSTX / 2)) * 2;
+  const int ly = threadIdx.x / (kSTX / kSNO), lx = (threadIdx.x % (kSTX / kSNO)) * kSNO;
   const int oy = ty0 + ly, ox = tx0 + lx;
   if (oy >= a.H || ox >= a.W) return;
-  T s0a = T(0), s0b = T(0), s1a = T(0), s1b = T(0);
+  T s0[kSNO], s1[kSNO];
+#pragma unroll
+  for (int u = 0; u < kSNO; ++u) s0[u] = s1[u] = T(0);
 #pragma unroll
   for (int p = 0; p < K; ++p) {
-    T r0[K + 1], r1[TWO ? K + 1 : 1];
+    T r0[K + kSNO - 1], r1[TWO ? K + kSNO - 1 : 1];
 #pragma unroll
-    for (int q = 0; q <= K; ++q) {
+    for (int q = 0; q < K + kSNO - 1; ++q) {
       r0[q] = tile0[(ly + p) * LW + lx + q];
       if (TWO) r1[q] = tile1[(ly + p) * LW + lx + q];
     }
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       const T kv = taps.k[p * K + q];
-      s0a += kv * r0[q];
-      s0b += kv * r0[q + 1];
-      if (TWO) {
-        s1a += kv * r1[q];
-        s1b += kv * r1[q + 1];
+#pragma unroll
+      for (int u = 0; u < kSNO; ++u) {
+        s0[u] += kv * r0[q + u];
+        if (TWO) s1[u] += kv * r1[q + u];
       }
     }
   }
@@ -194,8 +203,10 @@ __global__ __launch_bounds__(kBlock) void stencil_k_kernel(StencilArgs a, Taps<T
   const size_t o = pbase + static_cast<size_t>(oy) * a.W + ox;
   const bool uses_aux = MODE == S_B_MINUS || MODE == S_TANH_WRES || MODE == S_TANH_JTW ||
                         MODE == S_TANH_HESS;
-  out[o] = stencil_out<T, MODE>(s0a, s1a, uses_aux ? aux[o] : T(0), g, tg);
-  if (ox + 1 < a.W) out[o + 1] = stencil_out<T, MODE>(s0b, s1b, uses_aux ? aux[o + 1] : T(0), g, tg);
+#pragma unroll
+  for (int u = 0; u < kSNO; ++u)
+    if (ox + u < a.W)
+      out[o + u] = stencil_out<T, MODE>(s0[u], s1[u], uses_aux ? aux[o + u] : T(0), g, tg);
 }
 
 template <typename T, int K>
@@ -249,9 +260,9 @@ int stencil_dispatch(const StencilArgs& a, const double* taps_host, hipStream_t 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void extrap_kernel(const T* x, const T* xp, T* z,
                                                       const double* beta_eff, const int* gate,
-                                                      long long per) {
+                                                      int mask, long long per) {
   const int img = blockIdx.y;
-  if (gate && gate[img] == G_DONE) return;
+  if (gate && ((1 << gate[img]) & mask) == 0) return;
   const T b = static_cast<T>(beta_eff[img]);
   const size_t base = static_cast<size_t>(img) * per;
   for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < per;
@@ -261,15 +272,40 @@ __global__ __launch_bounds__(kBlock) void extrap_kernel(const T* x, const T* xp,
   }
 }
 
+// An image whose phase is not updated this step waits: its two iterate
+// buffers trade places (the buffers' roles alternate with the step), so that
+// the next step again finds x^k in its x operand and x^(k-1) in its xn one.
+template <typename T>
+__device__ inline void swap_wait(const UpdateArgs& a, size_t base, long long lo, long long hi) {
+  T* x = const_cast<T*>(static_cast<const T*>(a.x)) + base;
+  T* xn = static_cast<T*>(a.xn) + base;
+  for (long long i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const T u = x[i], v = xn[i];
+    x[i] = v;
+    xn[i] = u;
+  }
+}
+
+// update image `img` this step (else it is finished, or waits: swap_wait)
+__device__ inline bool update_runs(const UpdateArgs& a, int img, bool* waits) {
+  const int gv = a.gate ? a.gate[img] : G_LOW;
+  *waits = a.gate && gv != G_DONE && ((1 << gv) & a.run_mask) == 0;
+  return !a.gate || ((1 << gv) & a.run_mask) != 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a) {
   const int img = blockIdx.y;
   const int blk = blockIdx.x;
-  if (a.gate && a.gate[img] == G_DONE) return;
   const size_t base = static_cast<size_t>(img) * a.per;
   const long long chunk = (a.per + a.nblk - 1) / a.nblk;
   const long long lo = blk * chunk;
   const long long hi = lo + chunk < a.per ? lo + chunk : a.per;
+  bool waits;
+  if (!update_runs(a, img, &waits)) {
+    if (waits) swap_wait<T>(a, base, lo, hi);
+    return;
+  }
   const T* x = static_cast<const T*>(a.x) + base;
   const T* z = static_cast<const T*>(a.z) + base;
   const T* gf = a.gf ? static_cast<const T*>(a.gf) + base : nullptr;
@@ -306,9 +342,10 @@ constexpr int kU = 4;
 
 __global__ __launch_bounds__(kBlock) void extrap_f4_kernel(const float4* x, const float4* xp,
                                                          float4* z, const double* beta_eff,
-                                                         const int* gate, long long per4) {
+                                                         const int* gate, int mask,
+                                                         long long per4) {
   const int img = blockIdx.y;
-  if (gate && gate[img] == G_DONE) return;
+  if (gate && ((1 << gate[img]) & mask) == 0) return;
   const float b = static_cast<float>(beta_eff[img]);
   const size_t base = static_cast<size_t>(img) * per4;
   const long long step = static_cast<long long>(gridDim.x) * kBlock;
@@ -346,12 +383,16 @@ __device__ inline void upd1(float x, float z, float g, float q, float tau, float
 __global__ __launch_bounds__(kBlock) void update_f4_kernel(UpdateArgs a) {
   const int img = blockIdx.y;
   const int blk = blockIdx.x;
-  if (a.gate && a.gate[img] == G_DONE) return;
   const long long per4 = a.per / 4;
   const size_t base = static_cast<size_t>(img) * per4;
   const long long chunk = (per4 + a.nblk - 1) / a.nblk;
   const long long lo = blk * chunk;
   const long long hi = lo + chunk < per4 ? lo + chunk : per4;
+  bool waits;
+  if (!update_runs(a, img, &waits)) {
+    if (waits) swap_wait<float4>(a, base, lo, hi);
+    return;
+  }
   const float4* x = static_cast<const float4*>(a.x) + base;
   const float4* z = static_cast<const float4*>(a.z) + base;
   const float4* gf = a.gf ? static_cast<const float4*>(a.gf) + base : nullptr;
@@ -407,6 +448,11 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   const int lane = threadIdx.x;
   ImgState s = a.st[i];
   if (s.done) return;
+  if (((1 << s.prec) & a.run_mask) == 0) {
+    // waiting: the update kernel moved x^k into the new buffer
+    if (lane == 0) a.st[i].last_buf = a.buf_index;
+    return;
+  }
   double s1 = 0.0, s0 = 0.0, nf = 0.0;
   const double* p = a.partials + static_cast<size_t>(i) * a.nblk * 3;
   for (int b = lane; b < a.nblk; b += 64) {
@@ -475,7 +521,9 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
     }
     gate = s.prec;
   }
-  if (a.history) a.history[static_cast<size_t>(a.step) * a.n + i] = rel;
+  // row = this image's own update count (steps it waited through have none)
+  if (a.history && s.it - 1 < a.history_rows)
+    a.history[static_cast<size_t>(s.it - 1) * a.n + i] = rel;
   a.st[i] = s;
   a.gate[i] = s.done ? G_DONE : gate;
   a.beta_eff[i] = s.beta_eff;
@@ -642,14 +690,14 @@ int launch_stencil(const StencilArgs& a, const double* taps_host, int dtype, hip
 }
 
 int launch_extrap(const void* x, const void* xp, void* z, const double* beta_eff,
-                  const int* gate, int n, long long per, int dtype, hipStream_t s) {
+                  const int* gate, int mask, int n, long long per, int dtype, hipStream_t s) {
   if (dtype == IDQ_F32 && vec4_ok(per, {x, xp, z})) {
     const long long per4 = per / 4;
     long long g = (per4 + kBlock * kU - 1) / (kBlock * kU);
     dim3 grid(static_cast<int>(g < 1 ? 1 : (g > 256 ? 256 : g)), n);
     extrap_f4_kernel<<<grid, kBlock, 0, s>>>(static_cast<const float4*>(x),
                                              static_cast<const float4*>(xp),
-                                             static_cast<float4*>(z), beta_eff, gate, per4);
+                                             static_cast<float4*>(z), beta_eff, gate, mask, per4);
     IDQ_HIP(hipGetLastError());
     return IDQ_OK;
   }
@@ -657,11 +705,11 @@ int launch_extrap(const void* x, const void* xp, void* z, const double* beta_eff
   if (dtype == IDQ_F64)
     extrap_kernel<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(x),
                                                   static_cast<const double*>(xp),
-                                                  static_cast<double*>(z), beta_eff, gate, per);
+                                                  static_cast<double*>(z), beta_eff, gate, mask, per);
   else
     extrap_kernel<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(x),
                                                  static_cast<const float*>(xp),
-                                                 static_cast<float*>(z), beta_eff, gate, per);
+                                                 static_cast<float*>(z), beta_eff, gate, mask, per);
   IDQ_HIP(hipGetLastError());
   return IDQ_OK;
 }

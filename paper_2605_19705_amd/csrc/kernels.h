@@ -113,15 +113,17 @@ struct StencilArgs {
   const void* aux;
   void* out;
   const int* gate;          // per solver image (nullable => always run)
+  int gate_mask;            // run plane p iff (1 << gate[p / plane_div]) & gate_mask
   int plane_div;            // solver image = plane / plane_div
   int mode;
 };
 int launch_stencil(const StencilArgs& a, const double* taps_host, int dtype, hipStream_t s);
 
 // ---- elementwise / reductions ---------------------------------------------
-// z = x + beta_eff[img] * (x - xp) over n images of `per` elements.
+// z = x + beta_eff[img] * (x - xp) over n images of `per` elements (images
+// with (1 << gate[img]) & mask only).
 int launch_extrap(const void* x, const void* xp, void* z, const double* beta_eff,
-                  const int* gate, int n, long long per, int dtype, hipStream_t s);
+                  const int* gate, int mask, int n, long long per, int dtype, hipStream_t s);
 
 // Fused update of the i-DEQ step and per-block float64 partial sums:
 //   xn = z - tau (gf + lambda q),  gf = (gf_is_point ? p - y : gf)
@@ -138,6 +140,7 @@ struct UpdateArgs {
   void* xn;
   double tau, lambda;
   const int* gate;
+  int run_mask;        // update image i iff (1 << gate[i]) & run_mask
   double* partials;    // [n][nblk][3]
   int nblk;
 };
@@ -159,9 +162,11 @@ struct FinalizeArgs {
   double beta, tol, restart_B2, switch_tol;
   int max_iter, fixed_iters, switch_patience;
   int use_mid;          // the bf16 phase hands over to a split-bf16 phase first
+  int run_mask;         // phases updated this step; other images wait unchanged
   int buf_index;        // ping-pong buffer holding the new iterate
-  double* history;      // nullable: [step][n] relative residuals
-  int step;             // global update index of this finalize
+  double* history;      // nullable: [update][n] relative residuals, `history_rows` rows
+  int history_rows;
+  int step;             // step index of this finalize
 };
 int launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // x_out[img] = bufs[st[img].last_buf][img]
