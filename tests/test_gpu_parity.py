@@ -216,6 +216,29 @@ def test_config2_split_refinement_reaches_oracle_fixed_point():
     assert e["split@1e-5"][0] < 5e-3
 
 
+def test_waiting_steps_leave_results_unchanged():
+    """With a bf16 start the float32 passes run only once a poll has seen an
+    image in that phase; an image that gets there between polls waits, its
+    iterate buffers trading places each step.  Polling after every step, no
+    image ever waits, and every kernel treats images independently in a fixed
+    order, so polling every 3 and 5 steps must give bit-identical iterates,
+    iteration counts and residual histories (4 images of 3 x 40 x 40)."""
+    layers, taps, y, P = config2_small(4, 40, 40)
+    tau = 0.9 / S.power_iteration(P, y, y, synth.random_field(12345, y.shape), 30)
+    ctx = _ctx(layers, "blur", taps)
+    yg = to_gpu(y, torch.float32)
+    kw = dict(beta=0.5, tau=tau, lam=1.0, tol=1e-4, max_iter=3000, conv_prec="bf16",
+              refine_prec="bf16x3", history=400)
+    x1, r1 = ctx.solve(yg, poll_every=1, **kw)
+    assert np.all(r1.status == 0) and np.all(r1.iters > r1.iters_low + r1.iters_mid)
+    for poll in (3, 5):
+        xp, rp = ctx.solve(yg, poll_every=poll, **kw)
+        assert np.array_equal(to_np(xp), to_np(x1)), poll
+        for f in ("iters", "iters_low", "iters_mid", "status"):
+            assert np.array_equal(getattr(rp, f), getattr(r1, f)), (poll, f)
+        assert np.array_equal(rp.history, r1.history, equal_nan=True), poll
+
+
 def test_config3_tanh_blur_trajectory_f32():
     layers = net_layers("gray16", 0)
     taps = synth.uniform_taps(7)
