@@ -45,7 +45,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4_t;
 constexpr int TH = 16, TW = 16;
 constexpr int HW_ = TW + 2, HH_ = TH + 2, NPIX = HW_ * HH_;
 
-template <int PREC, int CI, int CO>
+template <int PREC, int CI, int CO, int PRO = P_NONE>
 struct Cfg {
   static constexpr bool BF = PREC == PREC_BF16;      // bf16 activations in HBM
   static constexpr bool SPLIT = PREC == PREC_SPLIT;  // float activations, hi/lo bf16 operands
@@ -67,22 +67,26 @@ struct Cfg {
   static constexpr int PIXB = (SPLIT ? 2 : 1) * CIP * ES + (VEC ? 16 : 0);
   static constexpr int LDS_IN = (NPIX * PIXB + 15) / 16 * 16;
   // launch shape: 4 waves of 4 output rows, one workgroup per tile.  Split
-  // passes over 64 input channels run 8 waves of 2 rows instead (two waves per
-  // SIMD, so one wave's matrix-core work overlaps the other's staging and
-  // epilogue); with 64 output channels, two workgroups per tile each take half
-  // of them, so that both the hi and the lo weight fragments of that half fit
-  // in LDS beside the tile
-  static constexpr bool W8 = (SPLIT && CI == 64) || (PREC == PREC_F32 && CI <= 4 && CO == 64);
+  // passes over 64 input channels, and float32 passes from 3 or 64 channels to
+  // 64, run 8 waves of 2 rows instead (two waves per SIMD, so one wave's
+  // matrix-core work overlaps the other's staging and epilogue).  For 64 -> 64
+  // two workgroups per tile each take half of the output channels, so that the
+  // weight fragments of that half (hi and lo for split) fit in LDS beside the
+  // tile.  The float32 64-channel tangent pass keeps the 4-wave form: its
+  // doubled staging registers would spill at two waves per SIMD.
+  static constexpr bool F32W = PREC == PREC_F32 && CO == 64 &&
+                               (CI <= 4 || (CI == 64 && PRO == P_NONE));
+  static constexpr bool W8 = (SPLIT && CI == 64) || F32W;
   static constexpr int WAVES = W8 ? 8 : 4;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int RWV = TH / WAVES;         // output rows per wave
-  static constexpr int CSPLIT = (SPLIT && CI == 64 && CO == 64) ? 2 : 1;  // workgroups per tile
+  static constexpr int CSPLIT = (W8 && CI == 64 && CO == 64) ? 2 : 1;  // workgroups per tile
   static constexpr int NJW = NJ / CSPLIT;        // 16-channel blocks per workgroup
   static constexpr int WBYTES = NCH * NJW * 64 * 16;
   // weight fragments in LDS: always for bf16 operands (hi parts for split);
-  // float32 ones where they are small (else they come from L2, where a wait
-  // for one also waits for the halo and epilogue loads issued before it)
-  static constexpr bool WLDS = MBF || WBYTES <= 48 * 1024;
+  // float32 ones where they fit beside the tile (else they come from L2, where
+  // a wait for one also waits for the halo and epilogue loads issued before it)
+  static constexpr bool WLDS = MBF || LDS_IN + WBYTES <= 160 * 1024;
   // split lo fragments in LDS too where they fit, else read from L2 (where a
   // wait for one also waits for the next tile's halo loads issued before it)
   static constexpr bool WLO_LDS = SPLIT && LDS_IN + 2 * WBYTES <= 160 * 1024;
@@ -412,9 +416,9 @@ __device__ inline void epilogue_piece_pipe(const ConvArgs& a, __amdgpu_buffer_rs
 }
 
 template <int PREC, int CI, int CO, int PRO, int EPI>
-__global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_kernel(
+__global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfma_kernel(
     ConvArgs a, int ntx, int nty, int ntiles) {
-  using C = Cfg<PREC, CI, CO>;
+  using C = Cfg<PREC, CI, CO, PRO>;
   static_assert(!C::SPLIT || PRO == P_NONE, "split passes take plain operands");
   // bf16 row-reuse kernels run software-pipelined: the epilogue of the previous
   // tile is issued in pieces between the matrix-core groups of the current one,
@@ -769,7 +773,7 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO>::THREADS), 1) void conv_mfma_ker
 
 template <int PREC, int CI, int CO, int PRO, int EPI>
 int launch_shape(const ConvArgs& a, hipStream_t s) {
-  using C = Cfg<PREC, CI, CO>;
+  using C = Cfg<PREC, CI, CO, PRO>;
   static_assert(C::LDS <= 160 * 1024, "LDS budget");
   static_assert(CO > 4 || EPI == E_RES || EPI == E_SUB || EPI == E_ADD,
                 "thin outputs are NCHW state tensors");
