@@ -483,8 +483,9 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfm
     }
   };
   // halos in registers ahead of the LDS stage: one tile, or two for the 8-wave
-  // split shape (whose matrix-core work per tile is short next to the HBM
-  // latency of the next halo; the second buffer fits its register budget)
+  // shapes (split, and float32 from 3 or 64 channels), whose matrix-core work
+  // per tile is short next to the HBM latency of the next halo and whose
+  // second buffer fits the register budget
   constexpr int DEPTH = C::W8 ? 2 : 1;
   Prefetch<C, PRO> pf, pf2;
   int t1 = DEPTH > 1 ? next_open(t) : 0;
