@@ -38,18 +38,19 @@ METRIC = "restored 256^2 images/s at rel. residual 1e-4: BF16+warm-start vs FP32
 BF16_PEAK = 2.5e15     # MI355X dense bf16 matrix-core peak, FLOP/s
 F32_PEAK = 157.3e12    # MI355X dense fp32 matrix-core peak, FLOP/s
 FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
-# HBM bytes per launch of the 64->64 conv kernels in this solve, from the
-# FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/ (FETCH x 2.0,
-# WRITE x 1.0, the factors a 256 MiB device copy gives); a figure is valid only
-# while the kernel's device code is the one measured (sha256 of its sources),
-# else it is reported as null.
+# HBM bytes per output pixel of the 64->64 conv kernels in this solve, from
+# the FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/ (FETCH x 2.0,
+# WRITE x 1.0, the factors a 256 MiB device copy gives; bytes of the solve's
+# launches over the pixels they computed).  `traffic` is this figure times the
+# pixels per timed launch.  A figure is valid only while the kernel's device
+# code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
-    "conv64_bf16": {"bytes": 154664816,
-                    "sha256": "b0d5248e152f164a498ae52e915d6786c0e23caa5997cab127b7fffca2e1844f",
+    "conv64_bf16": {"bytes_per_px": 337.16,
+                    "sha256": "f3ed99c51f2dd133fa80a708e9a512fa784cdba1adb9eb807bf4c645d9aac774",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
-    "conv64_bf16x3": {"bytes": 218101403,
-                      "sha256": "4861daa9f69293691e242f9004d205a3e447979297ff5a288e367da569208805",
+    "conv64_bf16x3": {"bytes_per_px": 673.35,
+                      "sha256": "e285fdc3d0083bec2605f1d40aa07dc78d2c37cd381c120034d04608bc872b8d",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},
 }
@@ -305,7 +306,8 @@ def main():
         per_px = (512.0 + 768.0) / 2 if split else (256.0 + 384.0) / 2
         return {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": tr["bytes"] if sources_sha256(tr["sources"]) == tr["sha256"] else None,
+                "traffic": (tr["bytes_per_px"] * px / launches
+                            if sources_sha256(tr["sources"]) == tr["sha256"] else None),
                 "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": per_px * px / launches,
                 "kernel": "conv_mfma_kernel<%s, 64, 64>" % ("bf16x3" if split else "bf16"),

@@ -145,6 +145,7 @@ __global__ __launch_bounds__(kThinThreads, kThinWaves) void conv_thin_kernel(Con
         d.e[r][co] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
             re, static_cast<int>(e_off + static_cast<unsigned>((co * H + r) * W) * 4u), 0, 0));
   };
+  unsigned long long done_px = 0;  // pixels this wave computed (lane 0)
   auto compute = [&](const ThinItem<CO>& d, int it) {
     // the weight reads below are the same for every item: keep the compiler
     // from hoisting all 9 x CO of them into registers for the whole walk
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kThinThreads, kThinWaves) void conv_thin_kernel(Con
     if (a.work_px && lane == 0) {
       const int cols = W - sx * PPW < PPW ? W - sx * PPW : PPW;
       const int rows = H - y0 < R ? H - y0 : R;
-      atomicAdd(a.work_px, static_cast<unsigned long long>(rows * cols));
+      done_px += static_cast<unsigned long long>(rows * cols);
     }
   };
 
@@ -223,6 +224,8 @@ __global__ __launch_bounds__(kThinThreads, kThinWaves) void conv_thin_kernel(Con
     fetch(A, item);
     compute(A, item);
   }
+  // one counter update per wave (one per item would serialise on the address)
+  if (a.work_px && lane == 0 && done_px) atomicAdd(a.work_px, done_px);
 }
 
 template <int CI, int CO, int EPI>
