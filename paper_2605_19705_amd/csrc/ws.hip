@@ -143,24 +143,24 @@ __global__ void pool_kernel(const TA* in, TA* out, int n, int h, int w, int C) {
   }
 }
 
+// c[b][y][x][0:64] = e6[b][y/2][x/2][0:64], c[b][y][x][64:96] = e2[b][y][x][0:32]:
+// a copy in 16-byte vectors; blockIdx.x = image row (b, y), threads over
+// (x, vector) of that row
 template <typename TA>
 __global__ void upcat_kernel(const TA* e6, const TA* e2, TA* c, int n, int h, int w) {
-  // c[b][y][x][0:64] = e6[b][y/2][x/2][0:64], c[b][y][x][64:96] = e2[b][y][x][0:32]
-  const long long total = static_cast<long long>(n) * h * w * 96;
-  for (long long i = static_cast<long long>(blockIdx.x) * kB + threadIdx.x; i < total;
-       i += static_cast<long long>(gridDim.x) * kB) {
-    const int ch = static_cast<int>(i % 96);
-    const long long pix = i / 96;
-    const int x = static_cast<int>(pix % w);
-    const int y = static_cast<int>((pix / w) % h);
-    const int b = static_cast<int>(pix / (static_cast<long long>(w) * h));
-    float v;
-    if (ch < 64)
-      v = ldf(e6, ((static_cast<size_t>(b) * (h / 2) + y / 2) * (w / 2) + x / 2) * 64 + ch);
-    else
-      v = ldf(e2, static_cast<size_t>(pix) * 32 + (ch - 64));
-    stf(c, i, v);
-  }
+  constexpr int VPC = 16 / static_cast<int>(sizeof(TA));  // channels per vector
+  constexpr int G = 96 / VPC;                            // vectors per pixel
+  const int row = blockIdx.x;
+  const int b = row / h, y = row - (row / h) * h;
+  const int t = blockIdx.y * kB + threadIdx.x;
+  if (t >= w * G) return;
+  const int x = t / G, gi = t - (t / G) * G;
+  const int ch0 = gi * VPC;
+  const size_t pix = static_cast<size_t>(row) * w + x;
+  const TA* src = ch0 < 64
+      ? e6 + ((static_cast<size_t>(b) * (h / 2) + y / 2) * (w / 2) + x / 2) * 64 + ch0
+      : e2 + pix * 32 + (ch0 - 64);
+  *reinterpret_cast<uint4*>(c + pix * 96 + ch0) = *reinterpret_cast<const uint4*>(src);
 }
 
 // delta_e6 = sigma'(h) * (sum over the 2x2 block of gc[:, 0:64]), sigma' from a = e6
@@ -336,10 +336,14 @@ int ws_aux_launch(int which, const void* a0, const void* a1, const void* a2, voi
       break;
     }
     case 1: {
-      const long long tot = static_cast<long long>(n) * h * w * 96;
-      upcat_kernel<TA><<<grid_of(tot), kB, 0, s>>>(static_cast<const TA*>(a0),
-                                                   static_cast<const TA*>(a1), static_cast<TA*>(out),
-                                                   n, h, w);
+      const long long per_row = static_cast<long long>(w) * (96 / (16 / sizeof(TA)));
+      const long long rows = static_cast<long long>(n) * h;
+      if (rows > 0x7fffffff || (per_row + kB - 1) / kB > 65535)
+        return fail(IDQ_E_INVAL, "warm-start image too large");
+      dim3 grid(static_cast<unsigned>(rows), static_cast<unsigned>((per_row + kB - 1) / kB));
+      upcat_kernel<TA><<<grid, kB, 0, s>>>(static_cast<const TA*>(a0),
+                                           static_cast<const TA*>(a1), static_cast<TA*>(out),
+                                           n, h, w);
       break;
     }
     case 2: {
