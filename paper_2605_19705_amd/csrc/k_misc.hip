@@ -2,6 +2,7 @@
 // forward operator, the inertial extrapolation, the fused update with its
 // float64 residual partial sums, the per-image finalize step (stopping rule,
 // restart, precision phase) and deterministic float64 reductions.
+#include <cmath>
 #include <cstdint>
 #include <initializer_list>
 
@@ -226,8 +227,133 @@ int stencil_k_launch(const StencilArgs& a, const Taps<T>& tp, hipStream_t s) {
   return IDQ_OK;
 }
 
+// Rank-1 taps k[p][q] = u[p] v[q] (the Gaussian and box blurs): a horizontal
+// pass over the staged tile into LDS, then a vertical one, 2K FMAs per output
+// (plus the halo rows of the first pass) instead of K^2.
+template <typename T>
+struct SepTaps {
+  T u[kMaxTap], v[kMaxTap];
+};
+
+template <typename T, int MODE, int K>
+__global__ __launch_bounds__(kBlock) void stencil_sep_kernel(StencilArgs a, SepTaps<T> tp) {
+  constexpr int R = (K - 1) / 2, LH = kSTY + K - 1, LW = kSTX + K - 1;
+  constexpr bool TWO = MODE == S_TANH_HESS;
+  __shared__ T tile0[LH * LW];
+  __shared__ T tile1[TWO ? LH * LW : 1];
+  __shared__ T hb0[LH * kSTX];
+  __shared__ T hb1[TWO ? LH * kSTX : 1];
+  const int plane = blockIdx.z;
+  if (a.gate && ((1 << a.gate[plane / a.plane_div]) & a.gate_mask) == 0) return;
+  const int ty0 = blockIdx.y * kSTY, tx0 = blockIdx.x * kSTX;
+  const size_t pbase = static_cast<size_t>(plane) * a.H * a.W;
+  const T* in0 = static_cast<const T*>(a.in0) + pbase;
+  const T* in1 = static_cast<const T*>(a.in1) + (TWO ? pbase : 0);
+  for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+    const int ly = i / LW, lx = i - (i / LW) * LW;
+    const int gy = wrap1(ty0 - R + ly, a.H), gx = wrap1(tx0 - R + lx, a.W);
+    const size_t src = static_cast<size_t>(gy) * a.W + gx;
+    tile0[i] = in0[src];
+    if (TWO) tile1[i] = in1[src];
+  }
+  __syncthreads();
+  // horizontal: hb[row][x] = sum_q v[q] tile[row][x + q], kSNO outputs per thread
+  for (int i = threadIdx.x; i < LH * (kSTX / kSNO); i += kBlock) {
+    const int ly = i / (kSTX / kSNO), lx = (i % (kSTX / kSNO)) * kSNO;
+    T r0[K + kSNO - 1], r1[TWO ? K + kSNO - 1 : 1];
+#pragma unroll
+    for (int q = 0; q < K + kSNO - 1; ++q) {
+      r0[q] = tile0[ly * LW + lx + q];
+      if (TWO) r1[q] = tile1[ly * LW + lx + q];
+    }
+#pragma unroll
+    for (int u = 0; u < kSNO; ++u) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        s0 += tp.v[q] * r0[q + u];
+        if (TWO) s1 += tp.v[q] * r1[q + u];
+      }
+      hb0[ly * kSTX + lx + u] = s0;
+      if (TWO) hb1[ly * kSTX + lx + u] = s1;
+    }
+  }
+  __syncthreads();
+  // vertical: out[y][x] = sum_p u[p] hb[y + p][x]
+  const int ly = threadIdx.x / (kSTX / kSNO), lx = (threadIdx.x % (kSTX / kSNO)) * kSNO;
+  const int oy = ty0 + ly, ox = tx0 + lx;
+  if (oy >= a.H || ox >= a.W) return;
+  T s0[kSNO], s1[kSNO];
+#pragma unroll
+  for (int u = 0; u < kSNO; ++u) s0[u] = s1[u] = T(0);
+#pragma unroll
+  for (int p = 0; p < K; ++p)
+#pragma unroll
+    for (int u = 0; u < kSNO; ++u) {
+      s0[u] += tp.u[p] * hb0[(ly + p) * kSTX + lx + u];
+      if (TWO) s1[u] += tp.u[p] * hb1[(ly + p) * kSTX + lx + u];
+    }
+  const T g = static_cast<T>(a.gain), tg = tanh(g);
+  const T* aux = static_cast<const T*>(a.aux);
+  T* out = static_cast<T*>(a.out);
+  const size_t o = pbase + static_cast<size_t>(oy) * a.W + ox;
+  const bool uses_aux = MODE == S_B_MINUS || MODE == S_TANH_WRES || MODE == S_TANH_JTW ||
+                        MODE == S_TANH_HESS;
+#pragma unroll
+  for (int u = 0; u < kSNO; ++u)
+    if (ox + u < a.W)
+      out[o + u] = stencil_out<T, MODE>(s0[u], s1[u], uses_aux ? aux[o + u] : T(0), g, tg);
+}
+
+template <typename T, int K>
+int stencil_sep_launch(const StencilArgs& a, const SepTaps<T>& tp, hipStream_t s) {
+  dim3 grid((a.W + kSTX - 1) / kSTX, (a.H + kSTY - 1) / kSTY, a.NP);
+  switch (a.mode) {
+    case S_B: stencil_sep_kernel<T, S_B, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_BT: stencil_sep_kernel<T, S_BT, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_B_MINUS: stencil_sep_kernel<T, S_B_MINUS, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_A: stencil_sep_kernel<T, S_TANH_A, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_WRES: stencil_sep_kernel<T, S_TANH_WRES, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_JTW: stencil_sep_kernel<T, S_TANH_JTW, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    case S_TANH_HESS: stencil_sep_kernel<T, S_TANH_HESS, K><<<grid, kBlock, 0, s>>>(a, tp); break;
+    default: return fail(IDQ_E_INVAL, "bad stencil mode");
+  }
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+// k = u v^T within 1e-13 of the largest tap (u and v read from the row and
+// column of that tap); rounding then differs from the direct sum by ~1 ulp
+template <typename T>
+bool separable(const double* k, int kh, int kw, bool flip, SepTaps<T>* tp) {
+  int pr = 0, pc = 0;
+  double m = 0.0;
+  for (int p = 0; p < kh; ++p)
+    for (int q = 0; q < kw; ++q)
+      if (std::fabs(k[p * kw + q]) > m) {
+        m = std::fabs(k[p * kw + q]);
+        pr = p;
+        pc = q;
+      }
+  if (!(m > 0.0)) return false;
+  double u[kMaxTap], v[kMaxTap];
+  for (int p = 0; p < kh; ++p) u[p] = k[p * kw + pc];
+  for (int q = 0; q < kw; ++q) v[q] = k[pr * kw + q] / k[pr * kw + pc];
+  for (int p = 0; p < kh; ++p)
+    for (int q = 0; q < kw; ++q)
+      if (std::fabs(k[p * kw + q] - u[p] * v[q]) > 1e-13 * m) return false;
+  for (int p = 0; p < kh; ++p) tp->u[p] = static_cast<T>(u[flip ? kh - 1 - p : p]);
+  for (int q = 0; q < kw; ++q) tp->v[q] = static_cast<T>(v[flip ? kw - 1 - q : q]);
+  return true;
+}
+
 template <typename T>
 int stencil_dispatch(const StencilArgs& a, const double* taps_host, hipStream_t s) {
+  if (a.kh == a.kw && (a.kh == 9 || a.kh == 7)) {
+    SepTaps<T> sp;
+    if (separable(taps_host, a.kh, a.kw, a.mode == S_BT, &sp))
+      return a.kh == 9 ? stencil_sep_launch<T, 9>(a, sp, s) : stencil_sep_launch<T, 7>(a, sp, s);
+  }
   Taps<T> tp;
   const bool flip = a.mode == S_BT;
   for (int p = 0; p < a.kh; ++p)

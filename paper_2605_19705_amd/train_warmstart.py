@@ -128,9 +128,9 @@ def main():
     ap.add_argument("--cfg-id", type=int, default=21)
     ap.add_argument("--solve-batch", type=int, default=128)
     ap.add_argument("--solve-tol", type=float, default=1e-5)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--lr-min", type=float, default=2e-5)
     ap.add_argument("--prec", default="bf16")
     ap.add_argument("--seed", type=int, default=0)

@@ -29,9 +29,20 @@ OPS = [("identity", None), ("blur", synth.gaussian_taps(9, 1.6)),
 
 @pytest.mark.parametrize("kind,taps", OPS)
 @pytest.mark.parametrize("shape", [(2, 3, 37, 45), (1, 3, 8, 8), (1, 1, 5, 3)])
-def test_operator_parity(kind, taps, shape, rng):
+@pytest.mark.parametrize("rank1", [False, True])
+def test_operator_parity(kind, taps, shape, rank1, rng):
+    """A, J_A^T and grad f against the oracle.  rank1: asymmetric separable taps
+    u v^T (the library's separable two-pass stencil, its flip for A^T); else
+    the symmetric taps plus noise (not separable: the direct stencil)."""
     if kind != "identity":
-        taps = taps + 0.01 * rng.standard_normal(taps.shape)   # break symmetry
+        if rank1:
+            u = rng.uniform(0.2, 1.0, taps.shape[0])
+            v = rng.uniform(0.2, 1.0, taps.shape[1])
+            taps = np.outer(u, v) / (u.sum() * v.sum())
+        else:
+            taps = taps + 0.01 * rng.standard_normal(taps.shape)   # break symmetry
+    elif rank1:
+        pytest.skip("no taps")
     op = O.Operator(kind, taps)
     ctx = _ctx(None, kind, taps)
     x = rng.uniform(0, 1, shape)
