@@ -58,6 +58,7 @@ def test_operator_parity(kind, taps, shape, rank1, rng):
 # the 3->32->32->64->32->3 net runs the 32-channel kernels (split ones included)
 @pytest.mark.parametrize("name,c,shape", [("gray16", 3, (2, 3, 19, 37)), ("rgb64", 3, (2, 3, 20, 36)),
                                           ("rgb64", 3, (1, 3, 8, 8)),
+                                          ("rgb64", 3, (1, 3, 13, 21)),
                                           ("c32", 3, (2, 3, 21, 34))])
 def test_grad_reg_parity(name, c, shape, rng):
     layers = (synth.he_normal_net([3, 32, 32, 64, 32, 3], 0, bias_seed=5) if name == "c32"
