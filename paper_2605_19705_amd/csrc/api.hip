@@ -737,7 +737,6 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
       fa.buf_index = (t + 1) % 2;
       fa.history = static_cast<double*>(hist);
       fa.history_rows = hist_len;
-      fa.step = t;
       fa.run_mask = run;
       IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
         IDQ_TRY(launch_update(ua, dtype, s));

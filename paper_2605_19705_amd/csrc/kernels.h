@@ -166,7 +166,6 @@ struct FinalizeArgs {
   int buf_index;        // ping-pong buffer holding the new iterate
   double* history;      // nullable: [update][n] relative residuals, `history_rows` rows
   int history_rows;
-  int step;             // step index of this finalize
 };
 int launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // x_out[img] = bufs[st[img].last_buf][img]

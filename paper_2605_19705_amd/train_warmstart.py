@@ -134,12 +134,17 @@ def main():
     ap.add_argument("--lr-min", type=float, default=2e-5)
     ap.add_argument("--prec", default="bf16")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--init", default=None,
+                    help="start from these parameters (.npy, packed like --out) instead of "
+                         "the seeded initialisation")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     ctx = deblur_context()
     ys, xs, _ = solver_pairs(ctx, args.pairs, args.size, args.cfg_id, args.solve_batch,
                              args.solve_tol, dev)
-    ws = WarmStart(synth.warmstart_init(args.seed), device=0)
+    p0 = (np.load(args.init).astype(np.float64) if args.init
+          else synth.warmstart_init(args.seed))
+    ws = WarmStart(p0, device=0)
     train(ws, ys, xs, args.val, args.epochs, args.batch, args.lr, args.lr_min, args.prec,
           args.seed)
     p = ws.get_params().astype(np.float32)
