@@ -113,10 +113,12 @@ def time_arm(torch, ctx, y, K, W, profile=None, every=1, check=True, **kw):
                 x=x, status=status)
 
 
-def also_measured(torch, poll, ws):
+def also_measured(torch, poll, ws, head_ctx=None, head_y=None, head_tau=None):
     """The other workloads the headline's measurement plan names, timed briefly
     (1 warm-up + 2 timed solves each): the tanh-blur problem in fp32 and the
-    4 x 3 x 512 x 512 deblurring batch from y, zero and the warm start."""
+    4 x 3 x 512 x 512 deblurring batch from y, zero and the warm start; and the
+    cost of one iteration of the headline batch in each arithmetic (10 fixed
+    iterations, every image active, the bf16 run held in its phase)."""
     import synth
     from paper_2605_19705_amd import IDQ
     dev = torch.device("cuda:0")
@@ -158,6 +160,16 @@ def also_measured(torch, poll, ws):
         res5[init] = summary(time_arm(torch, ctx5, y5, 2, 1, check=False, init=init, **kw,
                                       **extra), 4)
     out["deblur_4x3x512_by_init"] = res5
+
+    if head_ctx is not None:
+        per_it = {}
+        for prec, extra in (("bf16", dict(switch_tol=0.0, switch_patience=1 << 30)),
+                            ("bf16x3", {}), ("f32", {})):
+            r = time_arm(torch, head_ctx, head_y, 2, 1, check=False, conv_prec=prec,
+                         beta=0.5, tau=head_tau, lam=1.0, fixed_iters=10, poll_every=poll,
+                         **extra)
+            per_it[prec] = 1e3 * r["total_s"] / len(r["step_s"]) / 10
+        out["ms_per_iteration_8x3x256_by_arithmetic"] = per_it
     return out
 
 
@@ -320,7 +332,7 @@ def main():
     roofline_other = order[1] if len(order) > 1 else None
     phases = class_breakdown(torch, ctx, y, **head_kw)
 
-    also = None if args.no_also else also_measured(torch, args.poll, ws)
+    also = None if args.no_also else also_measured(torch, args.poll, ws, ctx, y, tau)
 
     cpu = None
     if not args.no_cpu_baseline:
