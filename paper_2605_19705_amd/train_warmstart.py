@@ -4,11 +4,13 @@ noise 0.01, 5-layer 64-channel SoftPlus regularizer with seed-0 He-normal
 weights, lambda 1, beta 0.5).
 
     python -m paper_2605_19705_amd.train_warmstart --out stage1.npy
-    python -m paper_2605_19705_amd.train_warmstart --out weights.npy \
+    python -m paper_2605_19705_amd.train_warmstart --out stage2.npy \
         --init stage1.npy --lr 1e-3 --lr-min 1e-5
+    ...
 
-(the packaged weights: a 60-epoch run from the seeded initialisation, then
-60 more epochs from its result at a lower learning rate)
+(the packaged weights: 60-epoch stages, the first from the seeded
+initialisation, each later one from the previous stage's result with peak
+learning rates 3e-3, 1e-3, 5e-4, 3e-4, 2e-4, ..., decaying to 1/100)
 
 Steps, all on the GPU through the library:
   1. ``--pairs`` synthetic 3 x size x size ground truths (generator id
