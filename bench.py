@@ -46,11 +46,11 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
     "conv64_bf16": {"bytes_per_px": 337.16,
-                    "sha256": "f3ed99c51f2dd133fa80a708e9a512fa784cdba1adb9eb807bf4c645d9aac774",
+                    "sha256": "0db8ae6212d6309a65e377a64719c181f494b59a176f2ced39b377150e2f7da6",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
     "conv64_bf16x3": {"bytes_per_px": 673.35,
-                      "sha256": "e285fdc3d0083bec2605f1d40aa07dc78d2c37cd381c120034d04608bc872b8d",
+                      "sha256": "471cb6a61e3e8ff4c7d805dc150d11d3a07db743571b6870f026514817bb8259",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},
 }

@@ -25,7 +25,7 @@ int Workspace::get(int slot, size_t bytes, void** out) {
     if (ptr[slot]) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) return fail(IDQ_E_HIP, std::string("sync: ") + hipGetErrorString(e));
-      hipFree(ptr[slot]);
+      (void)hipFree(ptr[slot]);
       ptr[slot] = nullptr;
       cap[slot] = 0;
     }
@@ -42,7 +42,7 @@ int Workspace::get(int slot, size_t bytes, void** out) {
 
 void Workspace::release() {
   for (int i = 0; i < W_NSLOTS; ++i) {
-    if (ptr[i]) hipFree(ptr[i]);
+    if (ptr[i]) (void)hipFree(ptr[i]);
     ptr[i] = nullptr;
     cap[i] = 0;
   }
@@ -92,9 +92,9 @@ int Profiler::flush() {
 
 void Profiler::release() {
   flush();
-  for (hipEvent_t e : pool) hipEventDestroy(e);
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   pool.clear();
-  if (dev_px) hipFree(dev_px);
+  if (dev_px) (void)hipFree(dev_px);
   dev_px = nullptr;
 }
 
@@ -151,7 +151,7 @@ void free_layers(idq_ctx* ctx) {
       void** all[] = {&L.fwd[p], &L.tr[p], &L.bias[p], &L.fwd_mfma[p], &L.tr_mfma[p]};
       for (void** q : all)
         if (*q) {
-          hipFree(*q);
+          (void)hipFree(*q);
           *q = nullptr;
         }
     }
@@ -568,7 +568,7 @@ int power_iteration(idq_ctx* ctx, const Geometry& g, int dtype, int prec, const 
 
 int ensure_host_gate(idq_ctx* ctx, int n) {
   if (ctx->host_gate_cap < n) {
-    if (ctx->host_gate) hipHostFree(ctx->host_gate);
+    if (ctx->host_gate) (void)hipHostFree(ctx->host_gate);
     ctx->host_gate = nullptr;
     IDQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->host_gate), sizeof(int) * n));
     ctx->host_gate_cap = n;
@@ -1083,12 +1083,12 @@ int idq_profile_read(idq_ctx* ctx, int cls, double* total_ms, long long* launche
 
 int idq_destroy(idq_ctx* ctx) {
   if (!ctx) return IDQ_OK;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
   ctx->prof.release();
   free_layers(ctx);
   ctx->ws.release();
-  if (ctx->host_gate) hipHostFree(ctx->host_gate);
+  if (ctx->host_gate) (void)hipHostFree(ctx->host_gate);
   delete ctx;
   return IDQ_OK;
 }

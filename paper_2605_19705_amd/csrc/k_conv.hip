@@ -10,7 +10,6 @@
 // Every pass is   acc[co](p) = sum_{ci, tap} W[co][ci][tap] * a[ci](p + off(tap))
 // with the operand a produced by the prologue (Pro) and the result consumed by
 // the epilogue (Epi); see kernels.h.
-#include <cstdlib>
 
 #include "kernels.h"
 
@@ -62,7 +61,6 @@ __global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
   }
   const TM* bias = static_cast<const TM*>(a.bias);
   const bool sp = a.act == IDQ_ACT_SOFTPLUS;
-#pragma unroll
   for (int j = 0; j < 16; ++j) {
     if (j >= nco) break;
     const int co = co0 + j;
@@ -134,15 +132,6 @@ static bool mfma_form_ok(const ConvArgs& a, int prec) {
   return in_ok && out_ok && jvp_ok;
 }
 
-static int force_direct() {
-  static int v = -1;
-  if (v < 0) {
-    const char* e = getenv("IDQ_FORCE_DIRECT");
-    v = (e && e[0] == '1') ? 1 : 0;
-  }
-  return v;
-}
-
 int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
   if (a.NI <= 0 || a.H <= 0 || a.W <= 0) return IDQ_OK;
   if (prec == PREC_SPLIT) {
@@ -151,8 +140,8 @@ int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
       return fail(IDQ_E_UNSUPPORTED, "split-bf16 conv pass of an unsupported form");
     return launch_conv_mfma(a, prec, s);
   }
-  if (!force_direct() && thin_supported(a, prec)) return launch_conv_thin(a, prec, s);
-  if (prec != PREC_F64 && a.wmfma && !force_direct() && mfma_supported(prec, a.CI, a.CO) &&
+  if (thin_supported(a, prec)) return launch_conv_thin(a, prec, s);
+  if (prec != PREC_F64 && a.wmfma && mfma_supported(prec, a.CI, a.CO) &&
       mfma_form_ok(a, prec))
     return launch_conv_mfma(a, prec, s);
   dim3 grid((a.H * a.W + 255) / 256, a.NI, (a.CO + 15) / 16);

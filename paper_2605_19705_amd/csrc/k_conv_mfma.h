@@ -591,7 +591,7 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfm
     for (int r = 0; r < RW; ++r)
 #pragma unroll
       for (int j = 0; j < NJW; ++j) acc[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    if (C::ROWS) {
+    if constexpr (C::ROWS) {
       // k = (dy*3 + dx) * CI + c*KC + slice: load the RW+2 input rows once per
       // (dx, c) and reuse them for dy = 0, 1, 2.  The weight fragments of the
       // next (dx, c, dy) group are fetched while the current group's MFMAs

@@ -557,14 +557,14 @@ int idq_ws_create(idq_ws** out, const double* params, long long count, int devic
 
 int idq_ws_destroy(idq_ws* ws) {
   if (!ws) return IDQ_OK;
-  hipSetDevice(ws->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(ws->device);
+  (void)hipDeviceSynchronize();
   for (auto& L : ws->L)
     for (int p = 0; p < 3; ++p)
       for (void* q : {L.dfwd[p], L.dtr[p], L.mfwd[p], L.mtr[p]})
-        if (q) hipFree(q);
+        if (q) (void)hipFree(q);
   for (float* q : {ws->master, ws->m, ws->v, ws->grad})
-    if (q) hipFree(q);
+    if (q) (void)hipFree(q);
   ws->ws.release();
   delete ws;
   return IDQ_OK;
