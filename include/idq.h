@@ -120,7 +120,13 @@ typedef struct {
                                (default 5)                                        */
     int    power_iters;     /* power iterations when tau == 0                    */
     const void* power_v0;   /* device, shape of y: power-iteration start vector  */
-    int    poll_every;      /* iterations enqueued between host polls            */
+    int    poll_every;      /* iterations enqueued between host polls of the
+                               per-image phases (default 8; <= 0 => 8).  Passes of a phase
+                               no image can be in are skipped; an image that
+                               reaches the float32 phase before its passes are
+                               launched waits (no update, no count) until they
+                               are.  The iterates do not depend on this value,
+                               only the launch count and the sync cost do.     */
     int    init;            /* IDQ_INIT_* used when x0 == NULL                    */
     idq_ws* ws;             /* warm-start network for IDQ_INIT_WARMSTART          */
     int    ws_prec;         /* IDQ_F32 | IDQ_BF16 for the warm-start inference    */
