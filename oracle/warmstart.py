@@ -13,8 +13,9 @@ Architecture (2-level conv encoder-decoder, 3x3 zero-padded convs, SoftPlus):
 Image height and width must be even.  Loss: mean squared error over all
 elements.  Optimiser: Adam with bias correction (beta1 0.9, beta2 0.999,
 eps 1e-8), the PyTorch defaults the paper trains with (App. D.1.3).
-Pins: central differences of the loss (tests/test_oracle_warmstart.py);
-the Adam step is its textbook definition (parity unpinned beyond that).
+Pins (tests/test_oracle_warmstart.py): central differences of the loss; the
+Adam step by closed forms (first step, a constant gradient over many steps,
+a gradient followed by a zero gradient).
 """
 import numpy as np
 

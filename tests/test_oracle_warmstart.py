@@ -1,5 +1,6 @@
 """Pins for oracle.warmstart: central differences of the MSE loss through the
-encoder-decoder, the pooling/upsampling adjoint pairs, and Adam's first step."""
+encoder-decoder, the pooling/upsampling adjoint pairs, and Adam's steps by
+closed forms (first step, a constant gradient, a gradient then a zero one)."""
 import numpy as np
 
 import synth
@@ -53,3 +54,27 @@ def test_adam_first_step_is_signed_lr():
     opt = WS.Adam(3, lr=1e-2)
     p1 = opt.step(p, g)
     np.testing.assert_allclose(p1, -1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    # with g fixed, the bias-corrected moments are exactly g and g^2 at every
+    # step t, so each step is lr * g / (|g| + eps) whatever t is
+    g = np.array([0.7, -1.5, 2e-4, -3e-2])
+    p0 = np.array([1.0, -2.0, 0.5, 0.0])
+    opt = WS.Adam(4, lr=3e-3)
+    p = p0
+    for _ in range(50):
+        p = opt.step(p, g)
+    np.testing.assert_allclose(p, p0 - 50 * 3e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+
+
+def test_adam_zero_gradient_after_one_step_uses_decayed_moments():
+    # m_2 = b1 (1 - b1) g and v_2 = b2 (1 - b2) g^2, so after bias correction
+    # mhat = b1 g / (1 + b1) and vhat = b2 g^2 / (1 + b2)
+    b1, b2, lr, eps = 0.9, 0.999, 1e-2, 1e-8
+    g = np.array([0.4, -3.0, 1e-5])
+    opt = WS.Adam(3, lr=lr, b1=b1, b2=b2, eps=eps)
+    p1 = opt.step(np.zeros(3), g)
+    p2 = opt.step(p1, np.zeros(3))
+    want = lr * (b1 / (1 + b1)) * g / (np.sqrt(b2 / (1 + b2)) * np.abs(g) + eps)
+    np.testing.assert_allclose(p1 - p2, want, rtol=1e-10)
