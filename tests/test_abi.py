@@ -69,3 +69,28 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[py]) == C.sizeof(T), py
         for fname, _ in T._fields_:
             assert int(got[f"{py}.{fname}"]) == getattr(T, fname).offset, (py, fname)
+
+
+def test_missing_library_fails_loudly():
+    """Without libidq.so the package raises instead of computing anything on the
+    CPU: constructing a solver context or a warm-start network is an error."""
+    import subprocess
+    import sys
+    code = "\n".join([
+        "import numpy as np",
+        "import paper_2605_19705_amd as P",
+        "P._lib.LIB_PATH = '/nonexistent/libidq.so'",
+        "layers = [(np.zeros((3, 3, 3, 3)), np.zeros(3))]",
+        "for make in (lambda: P.IDQ(layers, op_kind='identity'), lambda: P.WarmStart(layers)):",
+        "    try:",
+        "        make()",
+        "    except ImportError as e:",
+        "        assert 'libidq.so is missing' in str(e), e",
+        "        print('raised')",
+        "    else:",
+        "        raise SystemExit('no error')",
+    ])
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split() == ["raised", "raised"], r.stdout
