@@ -184,10 +184,26 @@ def class_breakdown(torch, ctx, y, **kw):
     return {k: {"ms": v[0], "launches": v[1]} for k, v in p.items()}
 
 
-def cpu_baseline(iters_per_image, sample_iters=3):
-    """The float64 oracle on the host: one 256x256 image of the same batch,
-    `sample_iters` i-DEQ iterations timed, scaled by the GPU fp32 arm's mean
-    iteration count to images per second."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(iters_per_image, sample_iters=10, repeats=3):
+    """The float64 oracle on the host, as it stands: one 256x256 image of the
+    headline batch, `sample_iters` i-DEQ iterations timed `repeats` times; the
+    median time per image-iteration, scaled by the GPU fp32 arm's mean iteration
+    count to rel 1e-4, gives images per second (the 8 images of the batch are
+    independent, so the batch takes 8 times as long).  ``cores`` is the BLAS
+    thread count the oracle's matrix products ran on."""
     import numpy as np
     import synth
     from oracle import operators as O, regularizer as R, solver as S
@@ -201,15 +217,17 @@ def cpu_baseline(iters_per_image, sample_iters=3):
     xt, nz = synth.make_batch(2, 1, 3, 256, 256)
     y = op.A(xt) + 0.01 * nz
     P = S.Problem(op, R.Net(layers), 1.0)
-    t0 = time.perf_counter()
-    S.ideq_solve(P, y, y, 0.5, 0.15, fixed_iters=sample_iters)
-    dt = time.perf_counter() - t0
-    t_iter = dt / sample_iters
+    runs = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        S.ideq_solve(P, y, y, 0.5, 0.15, fixed_iters=sample_iters)
+        runs.append(time.perf_counter() - t0)
+    t_iter = float(np.median(runs)) / sample_iters
     return {"value": 1.0 / (t_iter * iters_per_image), "unit": "images/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"1 of the 8 images, {sample_iters} float64 i-DEQ iterations "
-                      f"({t_iter:.2f} s per image-iteration), scaled by the fp32 arm's "
-                      f"{iters_per_image:.1f} iterations per image"}
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"image 0 of the 8-image batch, {sample_iters} float64 i-DEQ iterations, "
+                      f"median of {repeats} runs ({t_iter:.3f} s per image-iteration), scaled by "
+                      f"the fp32 arm's {iters_per_image:.1f} iterations per image"}
 
 
 def main():
@@ -295,7 +313,7 @@ def main():
     fp32 = None
     if not args.no_fp32:
         log("bench: fp32-plain arm")
-        fp32 = time_arm(torch, ctx, y, max(1, min(args.steps, 2)), 0, conv_prec="f32", **common)
+        fp32 = time_arm(torch, ctx, y, args.steps, args.warmup, conv_prec="f32", **common)
         fp32["value"] = n_img * len(fp32["step_s"]) / fp32["total_s"]
         log(f"bench: fp32 plain {fp32['value']:.2f} images/s, iterations {fp32['iters'][-1]}")
 
@@ -309,9 +327,10 @@ def main():
         avg_ms = ms / launches
         flops_per_launch = FLOP_PER_PX_64 * px / launches
         achieved = flops_per_launch / (avg_ms * 1e-3)
-        # split-bf16 runs three bf16 products per term: its ceiling is a third of
-        # the bf16 matrix-core peak, in the conv's own flops
-        peak = BF16_PEAK / 3.0 if split else BF16_PEAK
+        # the conv's own (algorithmic) flops against the dense bf16 matrix-core
+        # peak; split-bf16 issues three bf16 products per term, so it can reach at
+        # most a third of that peak, reported separately
+        peak = BF16_PEAK
         tr = TRAFFIC[cls]
         # bytes per pixel of an E_ACT pass (in + out) and an E_DELTA pass
         # (in + sigma operand + out), which the solve runs in equal numbers
@@ -324,6 +343,8 @@ def main():
                 "algorithmic_bytes": per_px * px / launches,
                 "kernel": "conv_mfma_kernel<%s, 64, 64>" % ("bf16x3" if split else "bf16"),
                 "launches": launches, "sampled_every": args.sample_every,
+                "matrix_core_products_per_flop": 3 if split else 1,
+                "frac_of_product_ceiling": achieved / (peak / (3.0 if split else 1.0)),
                 "avg_launch_us": avg_ms * 1e3,
                 "total_ms": ms, "flop_per_launch": flops_per_launch}
     rl = {c: conv_roofline(c) for c in ("conv64_bf16x3", "conv64_bf16")}
@@ -351,7 +372,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "bf16+bf16x3+f32" if args.refine == "bf16x3" else "bf16+f32",
         "data": "synthetic",
         "config": {
             "workload": "i-DEQ deblurring, 8x3x256x256, circular 9x9 gaussian (sigma 1.6), "
@@ -359,6 +380,14 @@ def main():
             "arm": ("bf16 convs, then split-bf16 (hi/lo, 3 products) convs to rel 1e-4, then "
                     "fp32 convs until an fp32 update has rel < 1e-4" if args.refine == "bf16x3"
                     else "bf16 convs, then fp32 convs to rel 1e-4") + f"; init={init}",
+            "arithmetic": "conv operands bf16 (fp32 accumulate), then split-bf16 (each fp32 "
+                          "operand as bf16 hi + lo, 3 products, fp32 accumulate), then fp32; "
+                          "state tensors fp32; per-image residuals, stopping test and "
+                          "reductions fp64",
+            "updates_per_image_by_arithmetic": {
+                "bf16": head["iters_low"][-1], "bf16x3": head["iters_mid"][-1],
+                "f32": [a - b - c for a, b, c in zip(head["iters"][-1], head["iters_low"][-1],
+                                                     head["iters_mid"][-1])]},
             "global_batch": n_img,
             "parallelism": "single GPU",
         },

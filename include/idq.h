@@ -139,6 +139,16 @@ typedef struct {
                                [k * n + i] = relative residual of image i after
                                update k+1 (NaN once the image has stopped)        */
     int    history_len;     /* rows of rel_history (updates recorded)             */
+    int    averaging;       /* 1: return the averaged iterate of Alg. 1's last
+                               step instead of x^K:
+                                 K_0 = argmin_{floor(K/2) < k < K-1} ||x^{k+1}-x^k||
+                                 (the first such k on ties),
+                                 x_hat = (K_0 + 1)^{-1} sum_{k=0..K_0} z^k,
+                               with K = fixed_iters; x^0 if the window is empty
+                               (K < 4).  Needs fixed_iters > 0, restart off and
+                               a single arithmetic (conv_prec != IDQ_BF16), else
+                               IDQ_E_UNSUPPORTED.  Remark 1 of the paper notes
+                               that the step may be omitted; 0 (default) omits it. */
 } idq_solve_opts;
 
 /* Per-image results of idq_solve (host array of n entries). */

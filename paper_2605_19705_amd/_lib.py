@@ -53,7 +53,7 @@ class SolveOpts(C.Structure):
                 ("power_iters", C.c_int), ("power_v0", C.c_void_p), ("poll_every", C.c_int),
                 ("init", C.c_int), ("ws", C.c_void_p), ("ws_prec", C.c_int),
                 ("refine_prec", C.c_int), ("rel_history", C.POINTER(C.c_double)),
-                ("history_len", C.c_int)]
+                ("history_len", C.c_int), ("averaging", C.c_int)]
 
 
 class SolveInfo(C.Structure):

@@ -193,7 +193,7 @@ class IDQ:
               fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
               switch_tol=2e-3, switch_patience=5, power_iters=30, power_v0=None,
               poll_every=8, init="y", ws=None, ws_prec="bf16", refine_prec="f32",
-              history=0):
+              history=0, averaging=False):
         o = L.SolveOpts()
         L.lib().idq_solve_opts_default(C.byref(o))
         o.beta, o.tau, o.lambda_, o.tol = float(beta), float(tau), float(lam), float(tol)
@@ -210,6 +210,7 @@ class IDQ:
         o.ws = ws._h.value if ws is not None else None
         o.ws_prec = _PREC[ws_prec]
         o.refine_prec = _PREC[refine_prec]
+        o.averaging = 1 if averaging else 0
         n = y.shape[0]
         hist = None
         if history:
@@ -254,6 +255,12 @@ class IDQSolve(torch.autograd.Function):
     Usage: IDQSolve.apply(y, theta, lam, ctx, solve_kwargs, bwd_kwargs) with
     theta the flat network parameters (float64 CPU tensor, loaded into the
     context before the solve) and lam a 0-d tensor.
+
+    The backward differentiates at the returned iterate as if it were the
+    fixed point (App. D.1), so the forward raises unless every image either
+    met the stopping rule or ran its fixed iteration budget (the paper's
+    training runs K iterations): an image that hit max_iter or produced a
+    non-finite iterate is an error here.
     """
 
     @staticmethod
@@ -262,6 +269,13 @@ class IDQSolve(torch.autograd.Function):
         kw = dict(solve_kwargs)
         kw["lam"] = float(lam)
         x, res = ctx.solve(y, **kw)
+        bad = [i for i, st in enumerate(res.status) if st not in (L.IDQ_ST_CONVERGED,
+                                                                   L.IDQ_ST_FIXED)]
+        if bad:
+            raise L.IDQError(res.code if res.code != L.IDQ_OK else L.IDQ_W_MAXITER,
+                             f"images {bad} did not reach a fixed point "
+                             f"(status {[int(res.status[i]) for i in bad]}); "
+                             "the implicit backward needs one")
         fctx.save_for_backward(x, y)
         fctx.idq = ctx
         fctx.tau = res.tau

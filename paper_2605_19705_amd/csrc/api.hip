@@ -592,6 +592,10 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   if (o->conv_prec == IDQ_BF16 && o->refine_prec != IDQ_F32 && o->refine_prec != IDQ_BF16X3)
     return fail(IDQ_E_INVAL, "refine_prec must be IDQ_F32 or IDQ_BF16X3");
   if (o->max_iter <= 0 && o->fixed_iters <= 0) return fail(IDQ_E_INVAL, "max_iter must be positive");
+  const bool averaging = o->averaging != 0;
+  if (averaging && (o->fixed_iters <= 0 || o->restart_B > 0.0 || o->conv_prec == IDQ_BF16))
+    return fail(IDQ_E_UNSUPPORTED,
+                "averaging needs fixed_iters > 0, restart off and a single conv arithmetic");
   const bool use_net = ctx->L > 0 && o->lambda != 0.0;
   const size_t es = elem_size(dtype);
   const size_t sbytes = static_cast<size_t>(n) * g.per * es;
@@ -631,6 +635,18 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     return fail(IDQ_E_INVAL, "bad init");
   }
   IDQ_TRY(copy_state(xb[0], xb[1], sbytes, s));
+  // averaging: running float64 sum of the z^k and the averaged output (x^0
+  // until the window's first step)
+  double* zsum = nullptr;
+  void* xhat = nullptr;
+  if (averaging) {
+    void* zs;
+    IDQ_TRY(ctx->ws.get(W_ZSUM, static_cast<size_t>(cnt) * sizeof(double), &zs));
+    IDQ_TRY(ctx->ws.get(W_XHAT, sbytes, &xhat));
+    zsum = static_cast<double*>(zs);
+    IDQ_HIP(hipMemsetAsync(zsum, 0, static_cast<size_t>(cnt) * sizeof(double), s));
+    IDQ_TRY(copy_state(xb[0], xhat, sbytes, s));
+  }
   // step size
   double tau = o->tau;
   if (tau <= 0.0) {
@@ -652,6 +668,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     st.prec = first_gate;
     st.rel = INFINITY;
     st.best_rel = INFINITY;
+    st.avg_best = INFINITY;
   }
   std::vector<int> hg(n, first_gate);
   std::vector<double> hb(n, 0.0);
@@ -694,6 +711,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   fa.max_iter = o->max_iter;
   fa.fixed_iters = o->fixed_iters;
   fa.use_mid = use_mid ? 1 : 0;
+  fa.avg_K = averaging ? o->fixed_iters : 0;
 
   int t = 0;
   while (t < host_limit) {
@@ -742,6 +760,10 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
         IDQ_TRY(launch_update(ua, dtype, s));
         return launch_finalize(fa, s);
       }));
+      // with averaging every image updates on every step, so step t is update t + 1
+      if (averaging)
+        IDQ_TRY(launch_average(z, zsum, xhat, static_cast<const ImgState*>(state), t + 1, n,
+                               g.per, dtype, s));
     }
     IDQ_HIP(hipMemcpyAsync(ctx->host_gate, gate, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     IDQ_HIP(hipStreamSynchronize(s));
@@ -759,8 +781,11 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     fin_live = !bf_start || anyfin;
     if (!any) break;
   }
-  IDQ_TRY(launch_gather_result(xb[0], xb[1], x_out, static_cast<const ImgState*>(state), n, g.per,
-                               dtype, s));
+  if (averaging)
+    IDQ_TRY(copy_state(xhat, x_out, sbytes, s));
+  else
+    IDQ_TRY(launch_gather_result(xb[0], xb[1], x_out, static_cast<const ImgState*>(state), n,
+                                 g.per, dtype, s));
   IDQ_HIP(hipMemcpyAsync(hs.data(), state, sizeof(ImgState) * n, hipMemcpyDeviceToHost, s));
   if (hist_len)
     IDQ_HIP(hipMemcpyAsync(o->rel_history, hist, sizeof(double) * n * hist_len,

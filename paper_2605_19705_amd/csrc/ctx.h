@@ -11,7 +11,7 @@ namespace idq {
 // Workspace slots.  Each slot is one device allocation that only grows.
 enum Slot {
   W_X0, W_X1, W_Z, W_GF, W_S, W_Q, W_R, W_RD, W_T, W_HG, W_HF, W_V, W_W, W_U, W_UP, W_UN,
-  W_PART, W_STATE, W_GATE, W_BETA, W_SCAL, W_WGPART, W_TMP0, W_TMP1, W_HIST,
+  W_PART, W_STATE, W_GATE, W_BETA, W_SCAL, W_WGPART, W_TMP0, W_TMP1, W_HIST, W_ZSUM, W_XHAT,
   W_H0,                              // W_H0 + l     : h_{l+1}         (l < L-1)
   W_HD0 = W_H0 + IDQ_MAX_LAYERS,     // W_HD0 + l    : h'_{l+1}
   W_DL0 = W_HD0 + IDQ_MAX_LAYERS,    // W_DL0 + l    : delta_{l+1}

@@ -592,6 +592,17 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
     nf += __shfl_down(nf, off, 64);
   }
   if (lane != 0) return;
+  // averaging window of Alg. 1: K_0 = argmin_{floor(K/2) < k < K-1} ||x^{k+1} - x^k||,
+  // the first such k on ties (strict <); k is this update's index (z^k -> x^{k+1})
+  s.avg_snap = 0;
+  if (a.avg_K > 0) {
+    const int k = s.it;
+    const double step = sqrt(s1);
+    if (k > a.avg_K / 2 && k < a.avg_K - 1 && step < s.avg_best) {
+      s.avg_best = step;
+      s.avg_snap = k + 1;
+    }
+  }
   s.it += 1;
   s.kr += 1;
   s.S += s1;
@@ -653,6 +664,24 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   a.st[i] = s;
   a.gate[i] = s.done ? G_DONE : gate;
   a.beta_eff[i] = s.beta_eff;
+}
+
+// zsum += z; xhat = zsum / avg_snap where the finalize marked a new best step.
+// Only images this step updated (their count equals it_now) take part.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void average_kernel(const T* z, double* zsum, T* xhat,
+                                                       const ImgState* st, int it_now,
+                                                       long long per) {
+  const int img = blockIdx.y;
+  if (st[img].it != it_now) return;
+  const int snap = st[img].avg_snap;
+  const size_t base = static_cast<size_t>(img) * per;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < per;
+       i += (long long)gridDim.x * kBlock) {
+    const double acc = zsum[base + i] + static_cast<double>(z[base + i]);
+    zsum[base + i] = acc;
+    if (snap > 0) xhat[base + i] = static_cast<T>(acc / static_cast<double>(snap));
+  }
 }
 
 template <typename T>
@@ -869,6 +898,19 @@ int launch_gather_result(const void* b0, const void* b1, void* out, const ImgSta
     gather_kernel<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(b0),
                                                  static_cast<const float*>(b1),
                                                  static_cast<float*>(out), st, per);
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+int launch_average(const void* z, double* zsum, void* xhat, const ImgState* st, int it_now,
+                   int n, long long per, int dtype, hipStream_t s) {
+  dim3 grid(grid_for(per), n);
+  if (dtype == IDQ_F64)
+    average_kernel<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(z), zsum,
+                                                   static_cast<double*>(xhat), st, it_now, per);
+  else
+    average_kernel<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(z), zsum,
+                                                  static_cast<float*>(xhat), st, it_now, per);
   IDQ_HIP(hipGetLastError());
   return IDQ_OK;
 }

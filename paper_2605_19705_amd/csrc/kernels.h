@@ -150,8 +150,9 @@ int launch_update(const UpdateArgs& a, int dtype, hipStream_t s);
 struct ImgState {
   int it, kr, status, done;
   int prec, it_low, stall, restarts;
-  int last_buf, it_mid, pad1, pad2;
+  int last_buf, it_mid, avg_snap, pad2;
   double S, rel, best_rel, beta_eff;
+  double avg_best;      // averaging: smallest ||x^{k+1} - x^k|| over the window
 };
 struct FinalizeArgs {
   int n, nblk;
@@ -166,8 +167,16 @@ struct FinalizeArgs {
   int buf_index;        // ping-pong buffer holding the new iterate
   double* history;      // nullable: [update][n] relative residuals, `history_rows` rows
   int history_rows;
+  int avg_K;            // > 0: averaging step over a run of avg_K updates (Alg. 1)
 };
 int launch_finalize(const FinalizeArgs& a, hipStream_t s);
+// Averaging step of Alg. 1, after each finalize of a run where every image
+// updates on every step: zsum[img] += z[img] for the images this step updated
+// (st.it == it_now); where the finalize marked a new smallest step in the
+// window (st.avg_snap = k + 1 > 0), xhat[img] = zsum[img] / (k + 1).  zsum is
+// float64 whatever the dtype.
+int launch_average(const void* z, double* zsum, void* xhat, const ImgState* st, int it_now,
+                   int n, long long per, int dtype, hipStream_t s);
 // x_out[img] = bufs[st[img].last_buf][img]
 int launch_gather_result(const void* b0, const void* b1, void* out, const ImgState* st,
                          int n, long long per, int dtype, hipStream_t s);

@@ -314,3 +314,53 @@ def test_backward_parity_on_crop():
     g = to_np(dth.reshape(1, 1, 1, -1)).ravel()
     assert np.max(np.abs(g - ref_th)) < 1e-7 * np.max(np.abs(ref_th))
     assert abs(dlam - ref_lam) < 1e-7 * abs(ref_lam)
+
+
+@pytest.mark.parametrize("K", [40, 3])
+def test_averaging_parity_f64(K):
+    """Alg. 1's averaging step (output (K_0 + 1)^{-1} sum_{k <= K_0} z^k) against
+    the oracle at 1e-10; K = 3 has an empty window, so the output is x^0."""
+    print(f"averaging step, config-1 denoising and a 2-image deblurring batch, K = {K}",
+          flush=True)
+    layers, y, P = config1_problem()
+    v0 = synth.random_field(12345, y.shape)
+    tau = 0.9 / S.power_iteration(P, y, y, v0, 30)
+    ref, _ = S.ideq_solve(P, y, y, 0.5, tau, fixed_iters=K, averaging=True)
+    ctx = _ctx(layers, "identity")
+    xg, res = ctx.solve(to_gpu(y), beta=0.5, tau=tau, lam=1.0, fixed_iters=K, averaging=True,
+                        conv_prec="f64")
+    assert np.all(res.iters == K)
+    assert np.max(np.abs(to_np(xg) - ref)) < 1e-10
+    if K < 4:
+        assert np.array_equal(to_np(xg), y)
+    # a batch of two deblurring images, the second one different
+    layers = net_layers("gray16", 1)
+    taps = synth.gaussian_taps(9, 1.6)
+    op = O.Operator("blur", taps)
+    xt, nz = synth.make_batch(2, 2, 1, 24, 20)
+    y = op.A(xt) + 0.01 * nz
+    P = S.Problem(op, R.Net(layers), 1.0)
+    tau = 0.9 / S.power_iteration(P, y, y, synth.random_field(12345, y.shape), 30)
+    ref, _ = S.ideq_solve(P, y, y, 0.5, tau, fixed_iters=K, averaging=True)
+    ctx = _ctx(layers, "blur", taps)
+    xg, _ = ctx.solve(to_gpu(y), beta=0.5, tau=tau, lam=1.0, fixed_iters=K, averaging=True,
+                      conv_prec="f64")
+    assert np.max(np.abs(to_np(xg) - ref)) < 1e-10
+    x32, _ = ctx.solve(to_gpu(y, torch.float32), beta=0.5, tau=tau, lam=1.0, fixed_iters=K,
+                       averaging=True, conv_prec="f32")
+    assert np.max(np.abs(to_np(x32) - ref)) < 1e-4
+
+
+def test_averaging_rejects_unsupported_options():
+    from paper_2605_19705_amd._lib import IDQError, IDQ_E_UNSUPPORTED
+    layers, y, P = config1_problem()
+    ctx = _ctx(layers, "identity")
+    yg = to_gpu(y)
+    for kw in (dict(max_iter=50), dict(fixed_iters=20, restart_B=1.0)):
+        with pytest.raises(IDQError) as e:
+            ctx.solve(yg, beta=0.5, tau=0.05, lam=1.0, averaging=True, conv_prec="f64", **kw)
+        assert e.value.code == IDQ_E_UNSUPPORTED
+    with pytest.raises(IDQError) as e:
+        ctx.solve(to_gpu(y, torch.float32), beta=0.5, tau=0.05, lam=1.0, averaging=True,
+                  fixed_iters=20, conv_prec="bf16")
+    assert e.value.code == IDQ_E_UNSUPPORTED
