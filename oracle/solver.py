@@ -6,6 +6,12 @@ One step of the i-DEQ operator (eq. ideq = RED step after eq. Momentum):
     x^{k+1} = z^k - tau (grad f(z^k, y) + lambda grad g(z^k))
 The ``grad_at='current'`` variant evaluates the gradient at x^k instead
 (heavy-ball form x^{k+1} = x^k + beta (x^k - x^{k-1}) - tau grad F(x^k)).
+The proximal variant i-DEQ-P (App. B, eq. red_prox, Alg. 2) replaces the
+gradient step on f by its proximal step:
+    x^{k+1} = prox_{tau f(., y)}(z^k - tau lambda grad g(z^k)).
+Its restart, stopping rule and averaging are read as those of Alg. 1 (Alg. 2
+writes the restart as x^{k-1} <- x^k only; with B = inf, as everywhere here,
+the two forms coincide).
 
 Readings of Alg. 1 taken here (each image of a batch is an independent run):
   * x^{-1} = x^0, so the first step has no inertia.
@@ -68,11 +74,12 @@ def _sq(a):
 
 def inertial_iterate(x0, grad_fn, beta, tau, tol=1e-4, max_iter=1000,
                      fixed_iters=None, restart_B=math.inf, grad_at="extrapolated",
-                     averaging=False, record=False):
+                     averaging=False, record=False, prox_fn=None):
     """Alg. 1's forward loop for a batch of independent images.
 
     grad_fn(p, idx) returns grad F at points p for the images ``idx`` of the
-    batch.  Returns (x_out, info) where info holds per-image arrays
+    batch.  With ``prox_fn`` (Alg. 2) grad_fn returns lambda grad g only and
+    the update is x^{k+1} = prox_fn(z - tau grad_fn(z, idx), idx).  Returns (x_out, info) where info holds per-image arrays
     ``iters``, ``rel`` (last relative residual), ``restarts``, ``status`` and,
     if ``record``, ``rels`` (list per image) and ``restart_at`` (global
     iteration counts after which a restart fired).
@@ -104,6 +111,8 @@ def inertial_iterate(x0, grad_fn, beta, tau, tol=1e-4, max_iter=1000,
         z = xa + beta * (xa - xpa)
         p = z if grad_at == "extrapolated" else xa
         xn = z - tau * grad_fn(p, idx)
+        if prox_fn is not None:
+            xn = prox_fn(xn, idx)
         k_of = it[idx]                         # index k of this step (z^k -> x^{k+1})
         d2 = _sq(xn - xa)
         s0 = _sq(xa)
@@ -155,14 +164,30 @@ def inertial_iterate(x0, grad_fn, beta, tau, tol=1e-4, max_iter=1000,
     return out, info
 
 
-def ideq_solve(problem, y, x0, beta, tau, **kw):
-    """i-DEQ forward pass on a batch: Alg. 1 with grad F = grad f + lambda grad g."""
-    y = np.asarray(y, dtype=np.float64)
+def ideq_solve(problem, y, x0, beta, tau, proximal=False, **kw):
+    """i-DEQ forward pass on a batch: Alg. 1 with grad F = grad f + lambda grad g,
+    or with ``proximal`` i-DEQ-P (Alg. 2): a gradient step on lambda g, then
+    the proximal step of f."""
+    y = np.asarray(y)
+    if not np.iscomplexobj(y):
+        y = y.astype(np.float64)
+    if not proximal:
+        def grad_fn(p, idx):
+            return problem.grad(p, y[idx])
 
-    def grad_fn(p, idx):
-        return problem.grad(p, y[idx])
+        return inertial_iterate(x0, grad_fn, beta, tau, **kw)
+    if kw.get("grad_at", "extrapolated") != "extrapolated":
+        raise ValueError("i-DEQ-P evaluates the gradient at z^k")
 
-    return inertial_iterate(x0, grad_fn, beta, tau, **kw)
+    def reg_fn(p, idx):
+        if problem.net is None or problem.lam == 0.0:
+            return np.zeros_like(p)
+        return problem.lam * problem.net.grad(p)
+
+    def prox_fn(v, idx):
+        return problem.op.prox(v, y[idx], tau)
+
+    return inertial_iterate(x0, reg_fn, beta, tau, prox_fn=prox_fn, **kw)
 
 
 def power_iteration(problem, x, y, v0, iters=30):

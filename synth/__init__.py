@@ -16,7 +16,7 @@ import numpy as np
 __all__ = [
     "ground_truth", "noise_field", "make_batch", "he_normal_net",
     "gaussian_taps", "uniform_taps", "net_channels", "warmstart_channels",
-    "random_field", "warmstart_init",
+    "random_field", "warmstart_init", "pixel_mask", "cartesian_mask",
 ]
 
 
@@ -146,3 +146,35 @@ def warmstart_init(seed: int = 0, out_scale: float = 0.1):
             W = W * out_scale
         out.append((W, np.zeros(cout)))
     return out
+
+
+def pixel_mask(seed, h: int, w: int, keep: float = 0.5) -> np.ndarray:
+    """Inpainting mask (h, w) of 0.0 / 1.0: each pixel is kept (1) independently
+    with probability ``keep``, from ``default_rng(seed).random((h, w)) < keep``.
+    A removed pixel loses all of its channels."""
+    return (np.random.default_rng(seed).random((h, w)) < keep).astype(np.float64)
+
+
+def cartesian_mask(seed, h: int, w: int, accel: int = 8, center_lines: int = None) -> np.ndarray:
+    """Cartesian k-space sampling mask (h, w) of 0.0 / 1.0 in the FFT's own
+    index order (frequency 0 at index 0): whole lines of fixed row frequency
+    ky are sampled, every column kx of a sampled line.
+
+    h // accel lines are sampled in total: the ``center_lines`` lowest
+    frequencies (default max(2, round(0.04 h)), the rows with |ky| smallest,
+    ky = 0 first) and then lines drawn uniformly without replacement from the
+    others by ``default_rng(seed).choice``.
+    """
+    n_lines = max(1, h // accel)
+    if center_lines is None:
+        center_lines = max(2, int(round(0.04 * h)))
+    center_lines = min(center_lines, n_lines)
+    freq = np.fft.fftfreq(h) * h                # signed row frequency of each index
+    order = np.argsort(np.abs(freq), kind="stable")
+    chosen = list(order[:center_lines])
+    rest = np.setdiff1d(np.arange(h), chosen)
+    extra = np.random.default_rng(seed).choice(rest, size=n_lines - center_lines, replace=False)
+    rows = np.zeros(h, dtype=np.float64)
+    rows[chosen] = 1.0
+    rows[extra] = 1.0
+    return np.repeat(rows[:, None], w, axis=1)
