@@ -241,6 +241,23 @@ int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_d
                  void* dtheta, double* dlambda, int n, int c, int h, int w, int dtype,
                  const idq_bwd_opts* opts, idq_bwd_info* info, void* stream);
 
+/* ---- allocation-free variant ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * idq_grad_data_noalloc computes exactly what idq_grad_data computes, with the
+ * same kernels, but stages its intermediate image (A(x) - y for the blur, the
+ * tanh-weighted residual for the tanh-blur) in a fixed device array of
+ * IDQ_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  It calls no allocating routine.  The intermediate
+ * image needs n*c*h*w elements of dtype; larger inputs return IDQ_E_INVAL
+ * with a message.  The identity operator needs no scratch (grad = x - y).
+ * Every call on one GPU shares that GPU's array, from every context: calls
+ * whose executions overlap on one GPU (concurrent streams, several host
+ * threads) race on it and must be serialised by the caller. */
+#define IDQ_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int idq_grad_data_noalloc(idq_ctx* ctx, const void* x, const void* y, void* grad,
+                          int n, int c, int h, int w, int dtype, void* stream);
+
 /* ---- device-time accounting ------------------------------------------------
  * When enabled, the library brackets its kernel launches with HIP events on
  * the launch stream and counts the output pixels each conv pass computed

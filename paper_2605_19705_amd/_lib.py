@@ -22,6 +22,7 @@ IDQ_MAX_LAYERS = 8
 IDQ_ST_CONVERGED, IDQ_ST_MAXITER, IDQ_ST_FIXED, IDQ_ST_NONFINITE = 0, 1, 2, -4
 IDQ_BWD_JFB, IDQ_BWD_IMPLICIT = 0, 1
 IDQ_PROF_ALL = 0x7fffffff
+IDQ_NOALLOC_SCRATCH_BYTES = 32 << 20
 PROF_CLASSES = {"conv64_bf16": 0, "conv64_f32": 1, "conv_other": 2, "stencil": 3, "update": 4,
                 "warmstart": 5, "conv64_bf16x3": 6}
 
@@ -29,7 +30,7 @@ EXPORTED = [
     "idq_last_error", "idq_version", "idq_solve_opts_default", "idq_create", "idq_destroy",
     "idq_set_params", "idq_num_params", "idq_apply_A", "idq_apply_AT", "idq_grad_data",
     "idq_grad_reg", "idq_hvp", "idq_lipschitz", "idq_solve", "idq_backward",
-    "idq_profile_enable", "idq_profile_sample", "idq_profile_read",
+    "idq_profile_enable", "idq_profile_sample", "idq_profile_read", "idq_grad_data_noalloc",
     "idq_ws_create", "idq_ws_destroy", "idq_ws_num_params", "idq_ws_get_params",
     "idq_ws_set_params", "idq_ws_forward", "idq_ws_train_step", "idq_ws_grad",
 ]
@@ -93,6 +94,7 @@ _SIGS = {
                    C.POINTER(SolveInfo), vp], ip),
     "idq_backward": ([vp, vp, vp, vp, vp, dp, ip, ip, ip, ip, ip, C.POINTER(BwdOpts),
                       C.POINTER(BwdInfo), vp], ip),
+    "idq_grad_data_noalloc": ([vp, vp, vp, vp, ip, ip, ip, ip, ip, vp], ip),
     "idq_profile_enable": ([vp, ip], ip),
     "idq_profile_sample": ([vp, ip], ip),
     "idq_profile_read": ([vp, ip, dp, C.POINTER(C.c_longlong), dp], ip),

@@ -163,6 +163,15 @@ class IDQ:
                                       _dtype_code(x), _stream()))
         return out
 
+    def grad_data_noalloc(self, x, y, out=None):
+        """grad f(x, y) through the allocation-free entry point; ``out`` may be a
+        preallocated tensor (the library itself allocates nothing)."""
+        if out is None:
+            out = torch.empty_like(x)
+        L.check(L.lib().idq_grad_data_noalloc(self._h, _ptr(x), _ptr(y), _ptr(out), *_shape4(x),
+                                              _dtype_code(x), _stream()))
+        return out
+
     def grad_reg(self, x, conv_prec=None, with_value=False):
         prec = _PREC[conv_prec] if conv_prec is not None else _dtype_code(x)
         out = torch.empty_like(x)

@@ -98,6 +98,48 @@ void Profiler::release() {
   dev_px = nullptr;
 }
 
+// Shape check shared by every entry point (declared in ctx.h).
+int check_shape(const idq_ctx* ctx, int n, int c, int h, int w, Geometry* g) {
+  if (n <= 0 || c <= 0 || h <= 0 || w <= 0) return fail(IDQ_E_INVAL, "non-positive shape");
+  g->n = n;
+  g->c = c;
+  g->h = h;
+  g->w = w;
+  g->per = static_cast<long long>(c) * h * w;
+  if (ctx->L > 0) {
+    const int c0 = ctx->ch[0];
+    if (c == c0) {
+      g->NI = n;
+      g->img_div = 1;
+    } else if (c0 == 1) {
+      g->NI = n * c;
+      g->img_div = c;
+    } else {
+      return fail(IDQ_E_INVAL, "image channels " + std::to_string(c) + " do not match the network's " +
+                                   std::to_string(c0));
+    }
+  } else {
+    g->NI = n;
+    g->img_div = 1;
+  }
+  return IDQ_OK;
+}
+
+// Stencil arguments of the forward operator for a geometry (declared in ctx.h).
+StencilArgs stencil_base(const idq_ctx* ctx, const Geometry& g, const int* gate) {
+  StencilArgs a{};
+  a.NP = g.n * g.c;
+  a.H = g.h;
+  a.W = g.w;
+  a.kh = ctx->kh;
+  a.kw = ctx->kw;
+  a.gain = ctx->gain;
+  a.gate = gate;
+  a.gate_mask = GM_ACTIVE;
+  a.plane_div = g.c;
+  return a;
+}
+
 namespace {
 
 // Arithmetic a layer pass actually runs in: split-bf16 only where a split
@@ -221,32 +263,6 @@ int pack_weights(idq_ctx* ctx) {
         IDQ_TRY(upload(&lw.tr_mfma[PREC_SPLIT], buf.data(), buf.size()));
       }
     }
-  }
-  return IDQ_OK;
-}
-
-int check_shape(const idq_ctx* ctx, int n, int c, int h, int w, Geometry* g) {
-  if (n <= 0 || c <= 0 || h <= 0 || w <= 0) return fail(IDQ_E_INVAL, "non-positive shape");
-  g->n = n;
-  g->c = c;
-  g->h = h;
-  g->w = w;
-  g->per = static_cast<long long>(c) * h * w;
-  if (ctx->L > 0) {
-    const int c0 = ctx->ch[0];
-    if (c == c0) {
-      g->NI = n;
-      g->img_div = 1;
-    } else if (c0 == 1) {
-      g->NI = n * c;
-      g->img_div = c;
-    } else {
-      return fail(IDQ_E_INVAL, "image channels " + std::to_string(c) + " do not match the network's " +
-                                   std::to_string(c0));
-    }
-  } else {
-    g->NI = n;
-    g->img_div = 1;
   }
   return IDQ_OK;
 }
@@ -450,20 +466,6 @@ int net_hvp(idq_ctx* ctx, const Geometry& g, int prec, const void* x, const void
 // ---------------------------------------------------------------------------
 // Forward operator passes
 // ---------------------------------------------------------------------------
-StencilArgs stencil_base(const idq_ctx* ctx, const Geometry& g, const int* gate) {
-  StencilArgs a{};
-  a.NP = g.n * g.c;
-  a.H = g.h;
-  a.W = g.w;
-  a.kh = ctx->kh;
-  a.kw = ctx->kw;
-  a.gain = ctx->gain;
-  a.gate = gate;
-  a.gate_mask = GM_ACTIVE;
-  a.plane_div = g.c;
-  return a;
-}
-
 int copy_state(const void* src, void* dst, size_t bytes, hipStream_t s) {
   IDQ_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
   return IDQ_OK;
@@ -999,6 +1001,8 @@ int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, in
     IDQ_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(IDQ_E_INVAL, "bad device index");
     IDQ_HIP(hipSetDevice(device));
+    // the allocation-free entry points' scratch address on this device
+    IDQ_TRY(noalloc_init_device(device));
     auto* ctx = new idq_ctx();
     ctx->device = device;
     if (net && net->n_layers > 0) {

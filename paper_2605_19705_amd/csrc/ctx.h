@@ -88,3 +88,13 @@ struct idq_ctx {
   int host_gate_cap = 0;
   idq::Profiler prof;
 };
+
+namespace idq {
+// Shape check of an entry point's image tensors (api.hip).
+int check_shape(const idq_ctx* ctx, int n, int c, int h, int w, Geometry* g);
+// Stencil arguments of the context's forward operator for a geometry (api.hip).
+StencilArgs stencil_base(const idq_ctx* ctx, const Geometry& g, const int* gate);
+// Resolves the device address of the fixed scratch array of the
+// allocation-free entry points on the current device (noalloc.hip).
+int noalloc_init_device(int device);
+}  // namespace idq
