@@ -99,7 +99,8 @@ class Trainer:
         (before the Adam step) and the accumulated (dtheta, dlambda)."""
         N = Y.shape[0]
         d = int(np.prod(Xs.shape[1:]))
-        X0 = Y if X0 is None else X0
+        if X0 is None:      # from y; MRI data live in k-space: the zero-filled A^T y
+            X0 = self.op.vjp(None, Y) if self.op.kind == "mri" else Y
         batch = N if batch is None else batch
         gth = np.zeros_like(self.theta)
         glam = 0.0
