@@ -60,6 +60,16 @@ extern "C" {
 #define IDQ_OP_IDENTITY    0   /* A(x) = x                                     */
 #define IDQ_OP_BLUR_CIRC   1   /* A x = k (*) x, circular cross-correlation     */
 #define IDQ_OP_TANH_BLUR   2   /* A(x) = tanh(gain * (k (*) x)) / tanh(gain)    */
+#define IDQ_OP_INPAINT     3   /* A x = M . x, M an h x w 0/1 pixel mask applied
+                                  to every channel (App. D.3.2)                  */
+#define IDQ_OP_MRI         4   /* A x = M . F x, F the unitary 2-D DFT of each
+                                  plane, M an h x w 0/1 k-space mask (App. D.3.1);
+                                  x is real (the phase is fixed to zero), y and
+                                  A(x) are complex: n*c*h*w (re, im) pairs of
+                                  dtype.  h and w: powers of two in [4, 1024]    */
+#define IDQ_OP_RICIAN      5   /* Rician likelihood instead of a Gaussian one
+                                  (App. D.3.3): A = identity and
+                                  f(x, y) = sum x^2/(2 s^2) - log I_0(x y / s^2) */
 
 #define IDQ_GRAD_AT_EXTRAPOLATED 0   /* gradient at z^k (Alg. 1)             */
 #define IDQ_GRAD_AT_CURRENT      1   /* gradient at x^k (heavy-ball form)    */
@@ -94,12 +104,21 @@ typedef struct {
 /* Forward operator A (paper, eq. inv_prob; the blur operators are the
  * deblurring and nonlinear workloads).  taps (host, float64): kh x kw row-major,
  * kh and kw odd, centred; the correlation is
- *   (B x)[i,j] = sum_{a,b} k[a,b] x[(i+a-(kh-1)/2) mod h, (j+b-(kw-1)/2) mod w]. */
+ *   (B x)[i,j] = sum_{a,b} k[a,b] x[(i+a-(kh-1)/2) mod h, (j+b-(kw-1)/2) mod w].
+ * For a Gaussian noise model f(x, y) = 1/2 ||A(x) - y||^2, so
+ * grad f = J_A^T (A(x) - y); for real x and complex MRI data the inner product
+ * is Re<u, v> and grad f = Re(F^H M (M F x - y)) (App. D.3.1-2).
+ * mask (host, float64, mh x mw of 0 or 1, copied at create time): the pixel
+ * mask of IDQ_OP_INPAINT, or the k-space mask of IDQ_OP_MRI in the DFT's own
+ * index order (frequency 0 at index 0); images must then be mh x mw. */
 typedef struct {
     int kind;                          /* IDQ_OP_*                              */
-    int kh, kw;                        /* taps size (ignored for identity)      */
+    int kh, kw;                        /* taps size (blurs only)                */
     const double* taps;                /* host, copied at create time           */
     double gain;                       /* tanh-blur gamma (e.g. 2.0)            */
+    const double* mask;                /* host; INPAINT and MRI only            */
+    int mh, mw;                        /* mask rows and columns                 */
+    double sigma;                      /* RICIAN: noise level sigma_y > 0       */
 } idq_op_desc;
 
 /* Options of idq_solve.  Fill with idq_solve_opts_default() first. */
@@ -149,6 +168,12 @@ typedef struct {
                                a single arithmetic (conv_prec != IDQ_BF16), else
                                IDQ_E_UNSUPPORTED.  Remark 1 of the paper notes
                                that the step may be omitted; 0 (default) omits it. */
+    int    proximal;        /* 1: i-DEQ-P (App. B, Alg. 2): the update is
+                                 x^{k+1} = prox_{tau f(., y)}(z^k - tau lambda grad g(z^k))
+                               with the closed-form prox of idq_prox_data; needs
+                               grad_at = EXTRAPOLATED and an operator with a
+                               closed form (identity, blur, inpainting, MRI),
+                               else IDQ_E_UNSUPPORTED.  0 (default): Alg. 1.     */
 } idq_solve_opts;
 
 /* Per-image results of idq_solve (host array of n entries). */
@@ -169,8 +194,14 @@ typedef struct {
     int    mode;              /* IDQ_BWD_*                                       */
     double tau, lambda;       /* the forward pass's step size and weight          */
     int    adjoint_max_iter;
-    double adjoint_tol;       /* on ||u_{j+1} - u_j|| / ||u_j|| (batch norms)     */
+    double adjoint_tol;       /* on ||u_{j+1} - u_j|| / ||u_j|| (batch norms),
+                                 tested every 8 iterations and at the last one    */
     double adjoint_beta;      /* inertia applied to the adjoint iteration          */
+    int    proximal;          /* 1: the fixed point is i-DEQ-P's (App. B, Alg. 2):
+                                 the map is P(z - tau lambda grad g(z)) with the
+                                 prox's Jacobian J_P = (I + tau A^T A)^{-1}, so
+                                 JFB uses J_P v and IMPLICIT solves
+                                 u = (I - tau lambda H_g) J_P u + v and uses J_P u */
 } idq_bwd_opts;
 
 typedef struct {
@@ -184,8 +215,10 @@ int idq_version(void);                     /* 10000*major + 100*minor + patch   
 void idq_solve_opts_default(idq_solve_opts* o);  /* host; beta .5, lambda 1, tol
                                               1e-4, max_iter 1000, F32, ...       */
 
-/* Create a context on HIP device `device`: copies the network and operator,
- * packs the weights for every conv arithmetic.  Synchronous. */
+/* Create a context on HIP device `device` for the problem y = A(x) + n solved
+ * as argmin f + lambda g (eq. inv_prob, eq. GS): copies the network and the
+ * operator, packs the weights for every conv arithmetic.  net may be NULL
+ * (g = 0).  Synchronous. */
 int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, int device);
 /* Destroy a context and free its device memory.  Synchronous. */
 int idq_destroy(idq_ctx* ctx);
@@ -195,14 +228,17 @@ int idq_set_params(idq_ctx* ctx, const double* params, long long count);
 /* Number of packed network parameters. */
 long long idq_num_params(const idq_ctx* ctx);
 
-/* Ax = A(x) (eq. inv_prob).  x, Ax: n*c*h*w of dtype. */
+/* Ax = A(x) (eq. inv_prob).  x, Ax: n*c*h*w of dtype (MRI: Ax complex, see
+ * IDQ_OP_MRI).  The Rician model has no operator (IDQ_E_UNSUPPORTED). */
 int idq_apply_A(idq_ctx* ctx, const void* x, void* Ax, int n, int c, int h, int w,
                 int dtype, void* stream);
-/* out = J_A(x)^T v, the adjoint (transposed Jacobian) of A at x; x may be NULL
- * for the linear operators.  This is the operator of grad f = J_A^T (A x - y). */
+/* out = J_A(x)^T v, the adjoint (transposed Jacobian) of A at x (eq. inv_prob,
+ * grad f = J_A^T (A x - y)); x may be NULL for the linear operators.  MRI: v
+ * complex, out = Re(F^H (M v)) real. */
 int idq_apply_AT(idq_ctx* ctx, const void* x, const void* v, void* out,
                  int n, int c, int h, int w, int dtype, void* stream);
-/* grad = grad_x f(x, y) = J_A(x)^T (A(x) - y). */
+/* grad = grad_x f(x, y) = J_A(x)^T (A(x) - y); Rician:
+ * x / s^2 - (y / s^2) I_1(x y / s^2) / I_0(x y / s^2) (App. D.3.3).  MRI: y complex. */
 int idq_grad_data(idq_ctx* ctx, const void* x, const void* y, void* grad,
                   int n, int c, int h, int w, int dtype, void* stream);
 /* grad = grad g(x) = r - J_N(x)^T r, r = x - N(x) (derivative of eq. GS).
@@ -210,12 +246,15 @@ int idq_grad_data(idq_ctx* ctx, const void* x, const void* y, void* grad,
  * synchronous.  conv_prec: IDQ_F64 (dtype F64) | IDQ_F32 | IDQ_BF16. */
 int idq_grad_reg(idq_ctx* ctx, const void* x, void* grad, double* g_val,
                  int n, int c, int h, int w, int dtype, int conv_prec, void* stream);
-/* out = H v with H = Hessian of g at x (which = 0) or of F at (x, y) with the
- * given lambda (which = 1; y may be NULL for which = 0). */
+/* out = H v with H = Hessian of g at x (which = 0) or of F = f + lambda g at
+ * (x, y) (which = 1; eq. inv_prob and the second derivative of eq. GS, the
+ * operator of the implicit backward, App. D.1); y may be NULL for which = 0. */
 int idq_hvp(idq_ctx* ctx, const void* x, const void* y, const void* v, void* out,
             double lambda, int which, int n, int c, int h, int w, int dtype,
             int conv_prec, void* stream);
-/* L = largest-magnitude eigenvalue of the batch Hessian of F at (x, y) by
+/* The step size of the i-DEQ iteration is tau = 0.9 / L (workload configuration;
+ * the paper states L_f = 1 for its linear operators, App. D.3.1-2).
+ * L = largest-magnitude eigenvalue of the batch Hessian of F at (x, y) by
  * `iters` steps of v <- Hv/||Hv|| from v0 (device, same shape), L = <v, Hv>.
  * Norms and dots in float64.  L (host) is written; synchronous. */
 int idq_lipschitz(idq_ctx* ctx, const void* x, const void* y, const void* v0,
@@ -231,6 +270,15 @@ int idq_lipschitz(idq_ctx* ctx, const void* x, const void* y, const void* v0,
 int idq_solve(idq_ctx* ctx, const void* y, const void* x0, void* x_out,
               int n, int c, int h, int w, int dtype, const idq_solve_opts* opts,
               idq_solve_info* info, void* stream);
+/* out = prox_{tau f(., y)}(v) = argmin_x f(x, y) + ||x - v||^2 / (2 tau) (App. B,
+ * eq. red_prox), for the operators with a closed form: identity, inpainting
+ * ((v + tau M y) / (1 + tau M), App. D.3.2), circular blur and MRI (the
+ * normal equations (I + tau A^T A) x = v + tau A^T y solved in the Fourier
+ * domain; for the real-valued MRI problem A^T A = F^H M_s F with
+ * M_s(k) = (M(k) + M(-k)) / 2).  Blur and MRI need power-of-two h, w in
+ * [4, 1024].  Tanh-blur and Rician: IDQ_E_UNSUPPORTED. */
+int idq_prox_data(idq_ctx* ctx, const void* v, const void* y, double tau, void* out,
+                  int n, int c, int h, int w, int dtype, void* stream);
 /* Gradient of a loss through the fixed point xbar (paper, App. D.1):
  * dl_dx = dloss/dxbar (device, image shaped).  Writes dtheta (device, dtype,
  * packed like the network parameters) and *dlambda (host).  IMPLICIT solves
@@ -241,6 +289,45 @@ int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_d
                  void* dtheta, double* dlambda, int n, int c, int h, int w, int dtype,
                  const idq_bwd_opts* opts, idq_bwd_info* info, void* stream);
 
+/* ---- training loop (Alg. 1, Alg. 2) ----------------------------------------
+ * One epoch of Alg. 1 over a dataset of N pairs (y_i, x*_i): the gradient of
+ * the epoch loss L = (1/N) sum_i mean_pixels (x_hat_i - x*_i)^2 is accumulated
+ * over the pairs, each x_hat_i the output of K fixed updates of the i-DEQ
+ * iteration (with restart and the averaging step as configured), then one Adam
+ * step (betas 0.9 / 0.999, eps 1e-8, bias-corrected) updates Theta = {theta,
+ * lambda}.  tau and beta stay fixed: their derivatives vanish at an exact fixed
+ * point (App. D.1.2).  The trainer keeps float64 master parameters and Adam
+ * moments on the device and loads the updated theta into its context after
+ * every step. */
+typedef struct idq_trainer idq_trainer;
+typedef struct {
+    int    mode;              /* IDQ_BWD_JFB | IDQ_BWD_IMPLICIT                    */
+    int    K;                 /* forward updates per pair (Alg. 1's budget)        */
+    double beta, tau;         /* inertia and step size of the forward pass         */
+    double restart_B;         /* <= 0: no restart                                   */
+    int    averaging;         /* 1: the averaging step gives x_hat                  */
+    int    proximal;          /* 1: i-DEQ-P (Alg. 2)                                */
+    int    conv_prec;         /* IDQ_F64 (dtype F64) | IDQ_F32                      */
+    int    learn_lambda;      /* 0: lambda stays fixed                              */
+    double lr_theta, lr_lambda;
+    int    adjoint_max_iter;
+    double adjoint_tol;
+    int    batch;             /* pairs per pass over the GPU (<= N; 0: all)        */
+} idq_train_opts;
+/* ctx: the problem (operator, network whose parameters are trained); lambda0:
+ * the initial weight.  The trainer uses ctx for every pass; it must outlive
+ * the trainer.  Synchronous. */
+int idq_train_create(idq_trainer** out, idq_ctx* ctx, double lambda0);
+int idq_train_destroy(idq_trainer* tr);
+/* One epoch.  Y: N measurements (device, dtype; MRI: complex), Xs: N targets,
+ * X0: N initial iterates or NULL (then y; MRI: A^T y).  loss (host): L before
+ * the step.  Synchronous. */
+int idq_train_epoch(idq_trainer* tr, const void* Y, const void* Xs, const void* X0, int N, int c,
+                    int h, int w, int dtype, const idq_train_opts* opts, double* loss,
+                    void* stream);
+/* Current parameters: theta (host, packed like idq_net_desc.params) and lambda. */
+int idq_train_get(idq_trainer* tr, double* theta, double* lambda);
+
 /* ---- allocation-free variant ---------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.
@@ -250,7 +337,9 @@ int idq_backward(idq_ctx* ctx, const void* xbar, const void* y, const void* dl_d
  * IDQ_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
  * until the process ends.  It calls no allocating routine.  The intermediate
  * image needs n*c*h*w elements of dtype; larger inputs return IDQ_E_INVAL
- * with a message.  The identity operator needs no scratch (grad = x - y).
+ * with a message.  The identity, inpainting and Rician terms need no scratch
+ * (their gradients are pixelwise); the MRI operator is not served
+ * (IDQ_E_UNSUPPORTED).
  * Every call on one GPU shares that GPU's array, from every context: calls
  * whose executions overlap on one GPU (concurrent streams, several host
  * threads) race on it and must be serialised by the caller. */

@@ -8,6 +8,6 @@ runs in hand-written HIP kernels behind the C ABI of ``include/idq.h``
 """
 from . import _lib
 from ._lib import IDQError, lib
-from .api import IDQ, IDQSolve, SolveResult, WarmStart, pack_layers
+from .api import IDQ, IDQSolve, SolveResult, Trainer, WarmStart, pack_layers
 
-__all__ = ["IDQ", "IDQSolve", "SolveResult", "WarmStart", "IDQError", "lib", "pack_layers", "_lib"]
+__all__ = ["IDQ", "IDQSolve", "SolveResult", "Trainer", "WarmStart", "IDQError", "lib", "pack_layers", "_lib"]

@@ -16,6 +16,7 @@ IDQ_E_INVAL, IDQ_E_NOMEM, IDQ_E_HIP, IDQ_E_NONFINITE, IDQ_E_UNSUPPORTED = -1, -2
 IDQ_F64, IDQ_F32, IDQ_BF16, IDQ_BF16X3 = 0, 1, 2, 3
 IDQ_ACT_SOFTPLUS, IDQ_ACT_IDENTITY = 0, 1
 IDQ_OP_IDENTITY, IDQ_OP_BLUR_CIRC, IDQ_OP_TANH_BLUR = 0, 1, 2
+IDQ_OP_INPAINT, IDQ_OP_MRI, IDQ_OP_RICIAN = 3, 4, 5
 IDQ_GRAD_AT_EXTRAPOLATED, IDQ_GRAD_AT_CURRENT = 0, 1
 IDQ_INIT_Y, IDQ_INIT_ZERO, IDQ_INIT_WARMSTART = 0, 1, 2
 IDQ_MAX_LAYERS = 8
@@ -29,7 +30,8 @@ PROF_CLASSES = {"conv64_bf16": 0, "conv64_f32": 1, "conv_other": 2, "stencil": 3
 EXPORTED = [
     "idq_last_error", "idq_version", "idq_solve_opts_default", "idq_create", "idq_destroy",
     "idq_set_params", "idq_num_params", "idq_apply_A", "idq_apply_AT", "idq_grad_data",
-    "idq_grad_reg", "idq_hvp", "idq_lipschitz", "idq_solve", "idq_backward",
+    "idq_grad_reg", "idq_hvp", "idq_lipschitz", "idq_solve", "idq_backward", "idq_prox_data",
+    "idq_train_create", "idq_train_destroy", "idq_train_epoch", "idq_train_get",
     "idq_profile_enable", "idq_profile_sample", "idq_profile_read", "idq_grad_data_noalloc",
     "idq_ws_create", "idq_ws_destroy", "idq_ws_num_params", "idq_ws_get_params",
     "idq_ws_set_params", "idq_ws_forward", "idq_ws_train_step", "idq_ws_grad",
@@ -43,7 +45,9 @@ class NetDesc(C.Structure):
 
 class OpDesc(C.Structure):
     _fields_ = [("kind", C.c_int), ("kh", C.c_int), ("kw", C.c_int),
-                ("taps", C.POINTER(C.c_double)), ("gain", C.c_double)]
+                ("taps", C.POINTER(C.c_double)), ("gain", C.c_double),
+                ("mask", C.POINTER(C.c_double)), ("mh", C.c_int), ("mw", C.c_int),
+                ("sigma", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -54,7 +58,7 @@ class SolveOpts(C.Structure):
                 ("power_iters", C.c_int), ("power_v0", C.c_void_p), ("poll_every", C.c_int),
                 ("init", C.c_int), ("ws", C.c_void_p), ("ws_prec", C.c_int),
                 ("refine_prec", C.c_int), ("rel_history", C.POINTER(C.c_double)),
-                ("history_len", C.c_int), ("averaging", C.c_int)]
+                ("history_len", C.c_int), ("averaging", C.c_int), ("proximal", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -66,7 +70,15 @@ class SolveInfo(C.Structure):
 class BwdOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tau", C.c_double), ("lambda_", C.c_double),
                 ("adjoint_max_iter", C.c_int), ("adjoint_tol", C.c_double),
-                ("adjoint_beta", C.c_double)]
+                ("adjoint_beta", C.c_double), ("proximal", C.c_int)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("mode", C.c_int), ("K", C.c_int), ("beta", C.c_double), ("tau", C.c_double),
+                ("restart_B", C.c_double), ("averaging", C.c_int), ("proximal", C.c_int),
+                ("conv_prec", C.c_int), ("learn_lambda", C.c_int), ("lr_theta", C.c_double),
+                ("lr_lambda", C.c_double), ("adjoint_max_iter", C.c_int),
+                ("adjoint_tol", C.c_double), ("batch", C.c_int)]
 
 
 class BwdInfo(C.Structure):
@@ -95,6 +107,11 @@ _SIGS = {
     "idq_backward": ([vp, vp, vp, vp, vp, dp, ip, ip, ip, ip, ip, C.POINTER(BwdOpts),
                       C.POINTER(BwdInfo), vp], ip),
     "idq_grad_data_noalloc": ([vp, vp, vp, vp, ip, ip, ip, ip, ip, vp], ip),
+    "idq_prox_data": ([vp, vp, vp, C.c_double, vp, ip, ip, ip, ip, ip, vp], ip),
+    "idq_train_create": ([C.POINTER(vp), vp, C.c_double], ip),
+    "idq_train_destroy": ([vp], ip),
+    "idq_train_epoch": ([vp, vp, vp, vp, ip, ip, ip, ip, ip, C.POINTER(TrainOpts), dp, vp], ip),
+    "idq_train_get": ([vp, dp, dp], ip),
     "idq_profile_enable": ([vp, ip], ip),
     "idq_profile_sample": ([vp, ip], ip),
     "idq_profile_read": ([vp, ip, dp, C.POINTER(C.c_longlong), dp], ip),

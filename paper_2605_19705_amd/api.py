@@ -18,7 +18,8 @@ from . import _lib as L
 _PREC = {"f64": L.IDQ_F64, "f32": L.IDQ_F32, "bf16": L.IDQ_BF16, "bf16x3": L.IDQ_BF16X3,
          L.IDQ_F64: L.IDQ_F64, L.IDQ_F32: L.IDQ_F32, L.IDQ_BF16: L.IDQ_BF16,
          L.IDQ_BF16X3: L.IDQ_BF16X3}
-_OPS = {"identity": L.IDQ_OP_IDENTITY, "blur": L.IDQ_OP_BLUR_CIRC, "tanh_blur": L.IDQ_OP_TANH_BLUR}
+_OPS = {"identity": L.IDQ_OP_IDENTITY, "blur": L.IDQ_OP_BLUR_CIRC, "tanh_blur": L.IDQ_OP_TANH_BLUR,
+        "inpaint": L.IDQ_OP_INPAINT, "mri": L.IDQ_OP_MRI, "rician": L.IDQ_OP_RICIAN}
 
 
 def _dtype_code(t):
@@ -37,6 +38,25 @@ def _ptr(t):
     if not t.is_contiguous():
         raise ValueError("tensors must be contiguous")
     return C.c_void_p(t.data_ptr())
+
+
+def _real_dtype(t):
+    """Element type of a real tensor, or of a complex tensor's (re, im) parts."""
+    if t.dtype == torch.complex128:
+        return torch.float64
+    if t.dtype == torch.complex64:
+        return torch.float32
+    return t.dtype
+
+
+def _kspace(t, like):
+    """A complex k-space tensor (MRI data) checked against the image tensor
+    ``like``: same (n, c, h, w) and matching element type."""
+    if not t.is_complex():
+        raise ValueError("MRI data must be a complex tensor")
+    if tuple(t.shape) != tuple(like.shape) or _real_dtype(t) != like.dtype:
+        raise ValueError("MRI data must match the image shape and precision")
+    return t
 
 
 def _stream():
@@ -72,7 +92,7 @@ class IDQ:
     """One library context: regularizer network + forward operator on a device."""
 
     def __init__(self, layers=None, act="softplus", op_kind="identity", taps=None, gain=2.0,
-                 device=0):
+                 mask=None, sigma=0.0, device=0):
         lib = L.lib()
         self.layers = [(np.asarray(W, np.float64), np.asarray(b, np.float64))
                        for W, b in (layers or [])]
@@ -93,11 +113,17 @@ class IDQ:
         od = L.OpDesc()
         od.kind = _OPS[op_kind]
         self._taps = None
-        if op_kind != "identity":
+        if op_kind in ("blur", "tanh_blur"):
             self._taps = np.ascontiguousarray(np.asarray(taps, np.float64))
             od.kh, od.kw = self._taps.shape
             od.taps = self._taps.ctypes.data_as(C.POINTER(C.c_double))
         od.gain = float(gain)
+        self._mask = None
+        if op_kind in ("inpaint", "mri"):
+            self._mask = np.ascontiguousarray(np.asarray(mask, np.float64))
+            od.mh, od.mw = self._mask.shape
+            od.mask = self._mask.ctypes.data_as(C.POINTER(C.c_double))
+        od.sigma = float(sigma)
         self.op_kind = op_kind
         h = C.c_void_p()
         L.check(lib.idq_create(C.byref(h), C.byref(nd) if self.layers else None, C.byref(od),
@@ -146,18 +172,35 @@ class IDQ:
 
     # ---- operators -------------------------------------------------------------
     def apply_A(self, x):
-        out = torch.empty_like(x)
+        """A(x); complex (same shape) for the MRI operator."""
+        if self.op_kind == "mri":
+            out = torch.empty(x.shape, device=x.device,
+                              dtype=torch.complex128 if x.dtype == torch.float64 else torch.complex64)
+        else:
+            out = torch.empty_like(x)
         L.check(L.lib().idq_apply_A(self._h, _ptr(x), _ptr(out), *_shape4(x), _dtype_code(x),
                                     _stream()))
         return out
 
     def apply_AT(self, v, x=None):
-        out = torch.empty_like(v)
+        """J_A(x)^T v; v complex for the MRI operator (the result is real)."""
+        out = torch.empty(v.shape, device=v.device, dtype=_real_dtype(v))
         L.check(L.lib().idq_apply_AT(self._h, _ptr(x), _ptr(v), _ptr(out), *_shape4(v),
-                                     _dtype_code(v), _stream()))
+                                     _dtype_code(out), _stream()))
+        return out
+
+    def prox_data(self, v, y, tau, out=None):
+        """prox_{tau f(., y)}(v) (closed forms; y complex for MRI)."""
+        if self.op_kind == "mri":
+            _kspace(y, v)
+        out = torch.empty_like(v) if out is None else out
+        L.check(L.lib().idq_prox_data(self._h, _ptr(v), _ptr(y), float(tau), _ptr(out),
+                                      *_shape4(v), _dtype_code(v), _stream()))
         return out
 
     def grad_data(self, x, y):
+        if self.op_kind == "mri":
+            _kspace(y, x)
         out = torch.empty_like(x)
         L.check(L.lib().idq_grad_data(self._h, _ptr(x), _ptr(y), _ptr(out), *_shape4(x),
                                       _dtype_code(x), _stream()))
@@ -202,14 +245,17 @@ class IDQ:
               fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
               switch_tol=2e-3, switch_patience=5, power_iters=30, power_v0=None,
               poll_every=8, init="y", ws=None, ws_prec="bf16", refine_prec="f32",
-              history=0, averaging=False):
+              history=0, averaging=False, proximal=False):
+        """The i-DEQ forward pass (Alg. 1; Alg. 2 with ``proximal``).  For MRI, y
+        is complex k-space data and the iterate is real (x0 default A^T y)."""
         o = L.SolveOpts()
         L.lib().idq_solve_opts_default(C.byref(o))
         o.beta, o.tau, o.lambda_, o.tol = float(beta), float(tau), float(lam), float(tol)
         o.max_iter, o.fixed_iters = int(max_iter), int(fixed_iters)
         o.restart_B = float(restart_B) if restart_B and np.isfinite(restart_B) else 0.0
         o.grad_at = L.IDQ_GRAD_AT_CURRENT if grad_at == "current" else L.IDQ_GRAD_AT_EXTRAPOLATED
-        o.conv_prec = _PREC[conv_prec] if conv_prec is not None else _dtype_code(y)
+        o.conv_prec = (_PREC[conv_prec] if conv_prec is not None
+                       else (L.IDQ_F64 if _real_dtype(y) == torch.float64 else L.IDQ_F32))
         o.switch_tol, o.switch_patience = float(switch_tol), int(switch_patience)
         o.power_iters = int(power_iters)
         o.power_v0 = _ptr(power_v0).value if power_v0 is not None else None
@@ -220,15 +266,19 @@ class IDQ:
         o.ws_prec = _PREC[ws_prec]
         o.refine_prec = _PREC[refine_prec]
         o.averaging = 1 if averaging else 0
+        o.proximal = 1 if proximal else 0
         n = y.shape[0]
+        rdt = _real_dtype(y)
+        if y.is_complex() != (self.op_kind == "mri"):
+            raise ValueError("complex k-space data goes with the MRI operator only")
         hist = None
         if history:
             hist = np.full((int(history), n), np.nan)
             o.rel_history = hist.ctypes.data_as(C.POINTER(C.c_double))
             o.history_len = int(history)
         info = (L.SolveInfo * n)()
-        x = out if out is not None else torch.empty_like(y)
-        code = L.lib().idq_solve(self._h, _ptr(y), _ptr(x0), _ptr(x), *_shape4(y), _dtype_code(y),
+        x = out if out is not None else torch.empty(y.shape, device=y.device, dtype=rdt)
+        code = L.lib().idq_solve(self._h, _ptr(y), _ptr(x0), _ptr(x), *_shape4(y), _dtype_code(x),
                                  C.byref(o), info, _stream())
         L.check(code, allow=(L.IDQ_OK, L.IDQ_W_MAXITER, L.IDQ_E_NONFINITE))
         res = SolveResult(iters=np.array([i.iters for i in info]),
@@ -242,8 +292,9 @@ class IDQ:
         return x, res
 
     def backward(self, xbar, y, dl_dx, tau, lam, mode="implicit", adjoint_max_iter=500,
-                 adjoint_tol=1e-6, adjoint_beta=0.0):
+                 adjoint_tol=1e-6, adjoint_beta=0.0, proximal=False):
         o = L.BwdOpts()
+        o.proximal = 1 if proximal else 0
         o.mode = L.IDQ_BWD_IMPLICIT if mode == "implicit" else L.IDQ_BWD_JFB
         o.tau, o.lambda_ = float(tau), float(lam)
         o.adjoint_max_iter, o.adjoint_tol = int(adjoint_max_iter), float(adjoint_tol)
@@ -304,6 +355,57 @@ class IDQSolve(torch.autograd.Function):
         ldt, ldev = fctx.lam_meta
         return (None, dtheta.to(device=tdev, dtype=tdt),
                 torch.tensor(dlam, dtype=ldt, device=ldev), None, None, None)
+
+
+class Trainer:
+    """The training loop of Alg. 1 / Alg. 2 (``idq_train_*``): Adam on the
+    network parameters of ``ctx`` and on lambda, one step per epoch."""
+
+    def __init__(self, ctx, lam0):
+        h = C.c_void_p()
+        L.check(L.lib().idq_train_create(C.byref(h), ctx._h, float(lam0)))
+        self._h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().idq_train_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def epoch(self, Y, Xs, X0=None, K=100, beta=0.5, tau=0.1, mode="jfb", restart_B=0.0,
+              averaging=False, proximal=False, learn_lambda=True, lr_theta=1e-3,
+              lr_lambda=1e-3, adjoint_max_iter=500, adjoint_tol=1e-6, batch=0):
+        """One epoch over the N pairs (Y[i], Xs[i]); returns the loss before the step."""
+        o = L.TrainOpts()
+        o.mode = L.IDQ_BWD_IMPLICIT if mode == "implicit" else L.IDQ_BWD_JFB
+        o.K, o.beta, o.tau = int(K), float(beta), float(tau)
+        o.restart_B = float(restart_B) if restart_B and np.isfinite(restart_B) else 0.0
+        o.averaging, o.proximal = int(bool(averaging)), int(bool(proximal))
+        o.conv_prec = _dtype_code(Xs)
+        o.learn_lambda = int(bool(learn_lambda))
+        o.lr_theta, o.lr_lambda = float(lr_theta), float(lr_lambda)
+        o.adjoint_max_iter, o.adjoint_tol = int(adjoint_max_iter), float(adjoint_tol)
+        o.batch = int(batch)
+        if Y.is_complex():
+            _kspace(Y, Xs)
+        loss = C.c_double(0.0)
+        L.check(L.lib().idq_train_epoch(self._h, _ptr(Y), _ptr(Xs), _ptr(X0), *_shape4(Xs),
+                                        _dtype_code(Xs), C.byref(o), C.byref(loss), _stream()))
+        return loss.value
+
+    def params(self):
+        """(theta as a flat float64 array, lambda)."""
+        theta = np.zeros(self.ctx.num_params)
+        lam = C.c_double(0.0)
+        L.check(L.lib().idq_train_get(self._h, theta.ctypes.data_as(C.POINTER(C.c_double)),
+                                      C.byref(lam)))
+        return theta, lam.value
 
 
 class WarmStart:

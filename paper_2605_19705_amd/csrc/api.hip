@@ -122,6 +122,13 @@ int check_shape(const idq_ctx* ctx, int n, int c, int h, int w, Geometry* g) {
     g->NI = n;
     g->img_div = 1;
   }
+  if ((ctx->op_kind == IDQ_OP_INPAINT || ctx->op_kind == IDQ_OP_MRI) &&
+      (h != ctx->mh || w != ctx->mw))
+    return fail(IDQ_E_INVAL, "images are " + std::to_string(h) + " x " + std::to_string(w) +
+                                 " but the operator's mask is " + std::to_string(ctx->mh) + " x " +
+                                 std::to_string(ctx->mw));
+  if (ctx->op_kind == IDQ_OP_MRI && !fft_supported(h, w))
+    return fail(IDQ_E_UNSUPPORTED, "the MRI operator needs power-of-two h and w in [4, 1024]");
   return IDQ_OK;
 }
 
@@ -471,14 +478,204 @@ int copy_state(const void* src, void* dst, size_t bytes, hipStream_t s) {
   return IDQ_OK;
 }
 
+int dt_index(int dtype) { return dtype == IDQ_F64 ? 0 : 1; }
+
+bool has_prox(int kind) {
+  return kind == IDQ_OP_IDENTITY || kind == IDQ_OP_BLUR_CIRC || kind == IDQ_OP_INPAINT ||
+         kind == IDQ_OP_MRI;
+}
+
+// Elementwise data-term pass over the whole batch.
+int datafit(idq_ctx* ctx, const Geometry& g, int dtype, int mode, const void* x, const void* y,
+            const void* v, void* out, double tau, hipStream_t s) {
+  DatafitArgs d{};
+  d.mode = mode;
+  d.count = static_cast<long long>(g.n) * g.per;
+  d.plane = static_cast<long long>(g.h) * g.w;
+  d.x = x;
+  d.y = y;
+  d.v = v;
+  d.mask = ctx->mask_dev[dt_index(dtype)];
+  d.out = out;
+  d.inv_s2 = ctx->sigma > 0.0 ? 1.0 / (ctx->sigma * ctx->sigma) : 0.0;
+  d.tau = tau;
+  return launch_datafit(d, dtype, s);
+}
+
+FftArgs fft_base(const Geometry& g) {
+  FftArgs f{};
+  f.NP = g.n * g.c;
+  f.H = g.h;
+  f.W = g.w;
+  f.scale = 1.0;
+  f.scale_r = 1.0;
+  return f;
+}
+
+// out = scale_r * Re(IDFT(mult . DFT(in0 + a1 in1 + a2 in2))) + b0 e0 over every
+// plane, with unnormalised DFTs (mult_mode M_MUL: mult, M_PROX: 1 / (1 + tau mult)).
+int fourier_pass(idq_ctx* ctx, const Geometry& g, int dtype, const void* in0, const void* in1,
+                 double a1, const void* in2, double a2, const void* mult, int mult_mode,
+                 double tau, double scale_r, const void* e0, double b0, void* out,
+                 hipStream_t s) {
+  void* cb;
+  IDQ_TRY(ctx->ws.get(W_CPLX, static_cast<size_t>(g.n) * g.per * 2 * elem_size(dtype), &cb));
+  FftArgs f = fft_base(g);
+  f.in0 = in0;
+  f.in1 = in1;
+  f.a1 = a1;
+  f.in2 = in2;
+  f.a2 = a2;
+  f.cbuf = cb;
+  IDQ_TRY(launch_fft_rows(f, R_FWD, dtype, s));
+  f.mult = mult;
+  f.mult_mode = mult_mode;
+  f.tau = tau;
+  IDQ_TRY(launch_fft_cols(f, C_FWD_MUL_INV, dtype, s));
+  f.out = out;
+  f.e0 = e0;
+  f.b0 = b0;
+  f.scale_r = scale_r;
+  return launch_fft_rows(f, R_INV, dtype, s);
+}
+
+// MRI: out = A^T v = Re(F^H (M v)) for complex k-space v (unitary DFT).
+int mri_adjoint(idq_ctx* ctx, const Geometry& g, int dtype, const void* v, void* out,
+                hipStream_t s) {
+  void* cb;
+  IDQ_TRY(ctx->ws.get(W_CPLX, static_cast<size_t>(g.n) * g.per * 2 * elem_size(dtype), &cb));
+  FftArgs f = fft_base(g);
+  f.cin = v;
+  f.cbuf = cb;
+  f.mult = ctx->mask_dev[dt_index(dtype)];
+  f.mult_mode = M_MUL;
+  IDQ_TRY(launch_fft_cols(f, C_MUL_INV, dtype, s));
+  f.out = out;
+  f.scale_r = 1.0 / std::sqrt(static_cast<double>(g.h) * g.w);
+  return launch_fft_rows(f, R_INV, dtype, s);
+}
+
+// MRI: Ax = M . F x (complex, unitary DFT).
+int mri_forward(idq_ctx* ctx, const Geometry& g, int dtype, const void* x, void* Ax,
+                hipStream_t s) {
+  void* cb;
+  IDQ_TRY(ctx->ws.get(W_CPLX, static_cast<size_t>(g.n) * g.per * 2 * elem_size(dtype), &cb));
+  FftArgs f = fft_base(g);
+  f.in0 = x;
+  f.cbuf = cb;
+  IDQ_TRY(launch_fft_rows(f, R_FWD, dtype, s));
+  f.cout = Ax;
+  f.mult = ctx->mask_dev[dt_index(dtype)];
+  f.mult_mode = M_MUL;
+  f.scale = 1.0 / std::sqrt(static_cast<double>(g.h) * g.w);
+  return launch_fft_cols(f, C_FWD_MUL, dtype, s);
+}
+
+// A^T y of a linear operator into the W_ATY slot (blur: B^T y; MRI: Re F^H M y).
+int data_aty(idq_ctx* ctx, const Geometry& g, int dtype, const void* y, void** aty,
+             hipStream_t s) {
+  IDQ_TRY(ctx->ws.get(W_ATY, static_cast<size_t>(g.n) * g.per * elem_size(dtype), aty));
+  if (ctx->op_kind == IDQ_OP_MRI) return mri_adjoint(ctx, g, dtype, y, *aty, s);
+  if (ctx->op_kind == IDQ_OP_BLUR_CIRC) {
+    StencilArgs b = stencil_base(ctx, g, nullptr);
+    b.in0 = y;
+    b.out = *aty;
+    b.mode = S_BT;
+    return launch_stencil(b, ctx->taps.data(), dtype, s);
+  }
+  return copy_state(y, *aty, static_cast<size_t>(g.n) * g.per * elem_size(dtype), s);
+}
+
+// |k^|^2 of the blur on the geometry's grid (computed once per size and dtype).
+int blur_spectrum(idq_ctx* ctx, const Geometry& g, int dtype, const void** spec, hipStream_t s) {
+  const int d = dt_index(dtype);
+  if (ctx->spec_dev[d] == nullptr || ctx->spec_h[d] != g.h || ctx->spec_w[d] != g.w) {
+    if (ctx->spec_dev[d]) {
+      IDQ_HIP(hipStreamSynchronize(s));
+      (void)hipFree(ctx->spec_dev[d]);
+      ctx->spec_dev[d] = nullptr;
+    }
+    IDQ_HIP(hipMalloc(&ctx->spec_dev[d], static_cast<size_t>(g.h) * g.w * elem_size(dtype)));
+    IDQ_TRY(launch_blur_spectrum(ctx->spec_dev[d], g.h, g.w, ctx->taps.data(), ctx->kh, ctx->kw,
+                                 dtype, s));
+    ctx->spec_h[d] = g.h;
+    ctx->spec_w[d] = g.w;
+  }
+  *spec = ctx->spec_dev[d];
+  return IDQ_OK;
+}
+
+// out = prox_{tau f(., y)}(v) with v = in0 + a1 in1 (in1 nullable), for the
+// operators with a closed form (App. B, eq. red_prox; App. D.3.1-2).  For the
+// Fourier forms `aty` = A^T y (from data_aty).
+int prox_apply(idq_ctx* ctx, const Geometry& g, int dtype, const void* in0, const void* in1,
+               double a1, const void* y, const void* aty, double tau, void* out,
+               hipStream_t s) {
+  switch (ctx->op_kind) {
+    case IDQ_OP_IDENTITY:
+    case IDQ_OP_INPAINT: {
+      DatafitArgs d{};
+      d.mode = D_MASK_PROX;
+      d.count = static_cast<long long>(g.n) * g.per;
+      d.plane = static_cast<long long>(g.h) * g.w;
+      d.x = in0;
+      d.v = in1;
+      d.a1 = a1;
+      d.y = y;
+      d.mask = ctx->op_kind == IDQ_OP_INPAINT ? ctx->mask_dev[dt_index(dtype)] : nullptr;
+      d.out = out;
+      d.tau = tau;
+      return launch_datafit(d, dtype, s);
+    }
+    case IDQ_OP_BLUR_CIRC: {
+      const void* spec;
+      IDQ_TRY(blur_spectrum(ctx, g, dtype, &spec, s));
+      return fourier_pass(ctx, g, dtype, in0, in1, a1, aty, tau, spec, M_PROX, tau,
+                          1.0 / (static_cast<double>(g.h) * g.w), nullptr, 0.0, out, s);
+    }
+    case IDQ_OP_MRI:
+      return fourier_pass(ctx, g, dtype, in0, in1, a1, aty, tau, ctx->msym_dev[dt_index(dtype)],
+                          M_PROX, tau, 1.0 / (static_cast<double>(g.h) * g.w), nullptr, 0.0,
+                          out, s);
+    default:
+      return fail(IDQ_E_UNSUPPORTED, "this data term has no closed-form proximal step");
+  }
+}
+
 // grad f(p, y) = J_A(p)^T (A(p) - y) into gf (not used for the identity,
-// whose gradient p - y the update kernel forms itself unless `force`).
+// whose gradient p - y the update kernel forms itself unless `force`).  For
+// MRI, `aty` = A^T y if already computed (else it is computed here).
 int data_grad(idq_ctx* ctx, const Geometry& g, int dtype, const void* p, const void* y, void* gf,
-              const int* gate, hipStream_t s, bool force, int mask = GM_ACTIVE) {
+              const int* gate, hipStream_t s, bool force, int mask = GM_ACTIVE,
+              const void* aty = nullptr) {
   const size_t sbytes = static_cast<size_t>(g.n) * g.per * elem_size(dtype);
-  if (ctx->op_kind == IDQ_OP_IDENTITY) {
-    if (force) IDQ_TRY(launch_axpbypcz(1.0, p, -1.0, y, 0.0, nullptr, gf, g.n * g.per, dtype, s));
-    return IDQ_OK;
+  switch (ctx->op_kind) {
+    case IDQ_OP_IDENTITY:
+      if (force) IDQ_TRY(launch_axpbypcz(1.0, p, -1.0, y, 0.0, nullptr, gf, g.n * g.per, dtype, s));
+      return IDQ_OK;
+    case IDQ_OP_INPAINT:
+      return profiled(ctx, PC_STENCIL, s, [&] {
+        return datafit(ctx, g, dtype, D_MASK_GRAD, p, y, nullptr, gf, 0.0, s);
+      });
+    case IDQ_OP_RICIAN:
+      return profiled(ctx, PC_STENCIL, s, [&] {
+        return datafit(ctx, g, dtype, D_RICIAN_GRAD, p, y, nullptr, gf, 0.0, s);
+      });
+    case IDQ_OP_MRI: {
+      if (!aty) {
+        void* t;
+        IDQ_TRY(data_aty(ctx, g, dtype, y, &t, s));
+        aty = t;
+      }
+      // F^H M_s F p - A^T y (the real part of F^H M (M F p - y) for real p)
+      return profiled(ctx, PC_STENCIL, s, [&] {
+        return fourier_pass(ctx, g, dtype, p, nullptr, 0.0, nullptr, 0.0,
+                            ctx->msym_dev[dt_index(dtype)], M_MUL, 0.0,
+                            1.0 / (static_cast<double>(g.h) * g.w), aty, -1.0, gf, s);
+      });
+    }
+    default:
+      break;
   }
   void* tmp;
   IDQ_TRY(ctx->ws.get(W_S, sbytes, &tmp));
@@ -501,7 +698,20 @@ int data_grad(idq_ctx* ctx, const Geometry& g, int dtype, const void* p, const v
 int data_hvp(idq_ctx* ctx, const Geometry& g, int dtype, const void* x, const void* y,
              const void* v, void* out, hipStream_t s) {
   const size_t sbytes = static_cast<size_t>(g.n) * g.per * elem_size(dtype);
-  if (ctx->op_kind == IDQ_OP_IDENTITY) return copy_state(v, out, sbytes, s);
+  switch (ctx->op_kind) {
+    case IDQ_OP_IDENTITY:
+      return copy_state(v, out, sbytes, s);
+    case IDQ_OP_INPAINT:   // A^T A = M for a 0/1 mask
+      return datafit(ctx, g, dtype, D_MASK_APPLY, v, nullptr, nullptr, out, 0.0, s);
+    case IDQ_OP_RICIAN:
+      return datafit(ctx, g, dtype, D_RICIAN_HESS, x, y, v, out, 0.0, s);
+    case IDQ_OP_MRI:
+      return fourier_pass(ctx, g, dtype, v, nullptr, 0.0, nullptr, 0.0,
+                          ctx->msym_dev[dt_index(dtype)], M_MUL, 0.0,
+                          1.0 / (static_cast<double>(g.h) * g.w), nullptr, 0.0, out, s);
+    default:
+      break;
+  }
   void* tmp;
   IDQ_TRY(ctx->ws.get(W_S, sbytes, &tmp));
   StencilArgs a = stencil_base(ctx, g, nullptr);
@@ -594,6 +804,11 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   if (o->conv_prec == IDQ_BF16 && o->refine_prec != IDQ_F32 && o->refine_prec != IDQ_BF16X3)
     return fail(IDQ_E_INVAL, "refine_prec must be IDQ_F32 or IDQ_BF16X3");
   if (o->max_iter <= 0 && o->fixed_iters <= 0) return fail(IDQ_E_INVAL, "max_iter must be positive");
+  const bool proximal = o->proximal != 0;
+  if (proximal && !has_prox(ctx->op_kind))
+    return fail(IDQ_E_UNSUPPORTED, "i-DEQ-P needs a data term with a closed-form proximal step");
+  if (proximal && o->grad_at != IDQ_GRAD_AT_EXTRAPOLATED)
+    return fail(IDQ_E_UNSUPPORTED, "i-DEQ-P evaluates the gradient at the extrapolated point");
   const bool averaging = o->averaging != 0;
   if (averaging && (o->fixed_iters <= 0 || o->restart_B > 0.0 || o->conv_prec == IDQ_BF16))
     return fail(IDQ_E_UNSUPPORTED,
@@ -621,15 +836,27 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     IDQ_HIP(hipMemcpyAsync(hist, nan.data(), sizeof(double) * nan.size(), hipMemcpyHostToDevice, s));
     IDQ_HIP(hipStreamSynchronize(s));
   }
+  // A^T y, once per solve, where the steps use it: the MRI gradient
+  // F^H M_s F z - A^T y and the Fourier proximal steps
+  const bool mri = ctx->op_kind == IDQ_OP_MRI;
+  void* aty = nullptr;
+  if (mri || (proximal && ctx->op_kind == IDQ_OP_BLUR_CIRC))
+    IDQ_TRY(data_aty(ctx, g, dtype, y, &aty, s));
+  void* pbuf = nullptr;
+  if (proximal) IDQ_TRY(ctx->ws.get(W_PROX, sbytes, &pbuf));
   // x^0 and x^{-1} = x^0
   if (x0) {
     IDQ_TRY(copy_state(x0, xb[0], sbytes, s));
+  } else if (o->init == IDQ_INIT_Y && mri) {
+    // k-space data: start from the zero-filled image A^T y
+    IDQ_TRY(copy_state(aty, xb[0], sbytes, s));
   } else if (o->init == IDQ_INIT_Y) {
     IDQ_TRY(copy_state(y, xb[0], sbytes, s));
   } else if (o->init == IDQ_INIT_ZERO) {
     IDQ_HIP(hipMemsetAsync(xb[0], 0, sbytes, s));
   } else if (o->init == IDQ_INIT_WARMSTART) {
-    if (!o->ws || dtype != IDQ_F32) return fail(IDQ_E_INVAL, "warm start needs a network and float32");
+    if (!o->ws || dtype != IDQ_F32 || mri)
+      return fail(IDQ_E_INVAL, "warm start needs a network, float32 and image-domain data");
     IDQ_TRY(profiled(ctx, PC_WARMSTART, s, [&] {
       return ws_forward_internal(o->ws, y, xb[0], n, c, h, w, o->ws_prec, s);
     }));
@@ -732,7 +959,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
                              dtype, s);
       }));
       const void* p = o->grad_at == IDQ_GRAD_AT_CURRENT ? xa : z;
-      if (!identity) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false, run));
+      if (!identity && !proximal) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false, run, aty));
       if (use_net) {
         if (low_live) IDQ_TRY(net_grad(ctx, g, IDQ_BF16, p, q, gp, 1 << G_LOW, s));
         if (mid_now) IDQ_TRY(net_grad(ctx, g, IDQ_BF16X3, p, q, gp, 1 << G_MID, s));
@@ -742,12 +969,23 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
       ua.n = n;
       ua.per = g.per;
       ua.x = xa;
-      ua.z = z;
-      ua.gf = identity ? nullptr : gf;
-      ua.p = p;
-      ua.y = y;
-      ua.q = use_net ? q : nullptr;
       ua.xn = xp;
+      if (proximal) {
+        // i-DEQ-P (Alg. 2): x^{k+1} = prox_{tau f}(z - tau lambda grad g(z)), formed
+        // over the whole batch; the update kernel takes it for the images it runs
+        IDQ_TRY(profiled(ctx, PC_STENCIL, s, [&] {
+          return prox_apply(ctx, g, dtype, z, use_net ? q : nullptr, -tau * o->lambda, y, aty,
+                            tau, pbuf, s);
+        }));
+        ua.z = pbuf;
+        ua.given = 1;
+      } else {
+        ua.z = z;
+        ua.gf = identity ? nullptr : gf;
+        ua.p = p;
+        ua.y = y;
+        ua.q = use_net ? q : nullptr;
+      }
       ua.tau = tau;
       ua.lambda = o->lambda;
       ua.gate = gp;
@@ -802,8 +1040,15 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     info[i].status = hs[i].status;
     info[i].rel = hs[i].rel;
     info[i].tau = tau;
-    if (hs[i].status == IDQ_ST_NONFINITE) rc = IDQ_E_NONFINITE;
-    else if (hs[i].status == IDQ_ST_MAXITER && rc == IDQ_OK) rc = IDQ_W_MAXITER;
+    if (hs[i].status == IDQ_ST_NONFINITE) {
+      if (rc != IDQ_E_NONFINITE)
+        set_error("image " + std::to_string(i) + " produced a non-finite iterate after " +
+                  std::to_string(hs[i].it) + " updates");
+      rc = IDQ_E_NONFINITE;
+    } else if (hs[i].status == IDQ_ST_MAXITER && rc == IDQ_OK) {
+      set_error("image " + std::to_string(i) + " reached max_iter");
+      rc = IDQ_W_MAXITER;
+    }
   }
   (void)cnt;
   return rc;
@@ -827,35 +1072,77 @@ int backward_impl(idq_ctx* ctx, const void* xbar, const void* y, const void* v, 
   IDQ_TRY(ctx->ws.get(W_W, sbytes, &hw));
   IDQ_TRY(ctx->ws.get(W_SCAL, 64, &scal));
   double* sc = static_cast<double*>(scal);
+  const bool proximal = o->proximal != 0;
+  if (proximal && !has_prox(ctx->op_kind))
+    return fail(IDQ_E_UNSUPPORTED, "i-DEQ-P needs a data term with a closed-form proximal step");
+  // J_P w = (I + tau A^T A)^{-1} w, the Jacobian of the proximal step: the
+  // proximal step with y = 0
+  void* zero = nullptr;
+  if (proximal) {
+    const size_t ybytes = sbytes * (ctx->op_kind == IDQ_OP_MRI ? 2 : 1);
+    IDQ_TRY(ctx->ws.get(W_PROX, ybytes, &zero));
+    IDQ_HIP(hipMemsetAsync(zero, 0, ybytes, s));
+  }
+  auto prox_lin = [&](const void* in, void* out) {
+    return prox_apply(ctx, g, dtype, in, nullptr, 0.0, zero, zero, o->tau, out, s);
+  };
   IDQ_TRY(copy_state(v, u, sbytes, s));
   int iters = 0;
   double rel = 0.0;
   if (o->mode == IDQ_BWD_IMPLICIT) {
     IDQ_TRY(copy_state(v, up, sbytes, s));
-    void* wv;
+    void *wv, *pw = nullptr;
     IDQ_TRY(ctx->ws.get(W_V, sbytes, &wv));
+    if (proximal) IDQ_TRY(ctx->ws.get(W_PW, sbytes, &pw));
+    // the relative change of each iteration goes to a device slot; the host
+    // reads them every kCheck iterations (and at the last), and the iteration
+    // that first met the tolerance ends the loop at the next check
+    constexpr int kCheck = 8;
+    void* relbuf;
+    IDQ_TRY(ctx->ws.get(W_HIST, sizeof(double) * 2 * kCheck, &relbuf));
+    double* rb = static_cast<double*>(relbuf);
     for (int j = 1; j <= o->adjoint_max_iter; ++j) {
-      // w = u + beta (u - up); un = w - tau H w + v
+      // w = u + beta (u - up)
       IDQ_TRY(launch_axpbypcz(1.0 + o->adjoint_beta, u, -o->adjoint_beta, up, 0.0, nullptr, wv, cnt,
                               dtype, s));
-      IDQ_TRY(obj_hvp(ctx, g, dtype, prec, xbar, y, wv, o->lambda, hw, s));
-      IDQ_TRY(launch_axpbypcz(1.0, wv, -o->tau, hw, 1.0, v, un, cnt, dtype, s));
+      if (!proximal) {
+        // un = w - tau H_F w + v
+        IDQ_TRY(obj_hvp(ctx, g, dtype, prec, xbar, y, wv, o->lambda, hw, s));
+        IDQ_TRY(launch_axpbypcz(1.0, wv, -o->tau, hw, 1.0, v, un, cnt, dtype, s));
+      } else {
+        // un = J_P w - tau lambda H_g J_P w + v
+        IDQ_TRY(prox_lin(wv, pw));
+        IDQ_TRY(net_hvp(ctx, g, prec, xbar, pw, hw, s));
+        IDQ_TRY(launch_axpbypcz(1.0, pw, -o->tau * o->lambda, hw, 1.0, v, un, cnt, dtype, s));
+      }
       // rel = ||un - u|| / ||u||
+      const int slot = (j - 1) % kCheck;
       IDQ_TRY(launch_axpbypcz(1.0, un, -1.0, u, 0.0, nullptr, up, cnt, dtype, s));
-      IDQ_TRY(dot(ctx, up, up, cnt, dtype, sc, s));
-      IDQ_TRY(dot(ctx, u, u, cnt, dtype, sc + 1, s));
-      double hsc[2];
-      IDQ_HIP(hipMemcpyAsync(hsc, sc, 16, hipMemcpyDeviceToHost, s));
-      IDQ_HIP(hipStreamSynchronize(s));
-      rel = std::sqrt(hsc[0] / std::max(hsc[1], 1e-300));
+      IDQ_TRY(dot(ctx, up, up, cnt, dtype, rb + 2 * slot, s));
+      IDQ_TRY(dot(ctx, u, u, cnt, dtype, rb + 2 * slot + 1, s));
       // rotate: up <- u, u <- un
       void* tmp = up;
       up = u;
       u = un;
       un = tmp;
       iters = j;
-      if (!(rel >= o->adjoint_tol)) break;
+      if (slot == kCheck - 1 || j == o->adjoint_max_iter) {
+        double hsc[2 * kCheck];
+        IDQ_HIP(hipMemcpyAsync(hsc, rb, sizeof(double) * 2 * (slot + 1), hipMemcpyDeviceToHost, s));
+        IDQ_HIP(hipStreamSynchronize(s));
+        bool met = false;
+        for (int q = 0; q <= slot; ++q) {
+          rel = std::sqrt(hsc[2 * q] / std::max(hsc[2 * q + 1], 1e-300));
+          if (!(rel >= o->adjoint_tol)) met = true;
+        }
+        if (met) break;
+      }
     }
+  }
+  // the vector the parameter gradient uses: u, or J_P u for i-DEQ-P
+  if (proximal) {
+    IDQ_TRY(prox_lin(u, un));
+    u = un;
   }
   // theta gradient from the forward-over-reverse pass along u
   void* hgout;
@@ -944,6 +1231,45 @@ int backward_impl(idq_ctx* ctx, const void* xbar, const void* y, const void* v, 
   return IDQ_OK;
 }
 
+void free_operator(idq_ctx* ctx) {
+  for (int d = 0; d < 2; ++d)
+    for (void** q : {&ctx->mask_dev[d], &ctx->msym_dev[d], &ctx->spec_dev[d]})
+      if (*q) {
+        (void)hipFree(*q);
+        *q = nullptr;
+      }
+}
+
+// Copies the 0/1 mask of an inpainting or MRI operator to the device in float64
+// and float32; for MRI also M_s(k) = (M(k) + M(-k)) / 2 (-k taken mod h, w),
+// the multiplier of A^T A = Re(F^H M F) on real images.
+int upload_mask(idq_ctx* ctx, const idq_op_desc* op) {
+  if (!op->mask || op->mh <= 0 || op->mw <= 0)
+    return fail(IDQ_E_INVAL, "mask operators need a mask and its size");
+  const int h = op->mh, w = op->mw;
+  const size_t cnt = static_cast<size_t>(h) * w;
+  for (size_t i = 0; i < cnt; ++i)
+    if (op->mask[i] != 0.0 && op->mask[i] != 1.0) return fail(IDQ_E_INVAL, "mask values must be 0 or 1");
+  if (op->kind == IDQ_OP_MRI && !fft_supported(h, w))
+    return fail(IDQ_E_UNSUPPORTED, "the MRI operator needs power-of-two h and w in [4, 1024]");
+  ctx->mh = h;
+  ctx->mw = w;
+  std::vector<double> sym(cnt);
+  for (int i = 0; i < h; ++i)
+    for (int j = 0; j < w; ++j)
+      sym[static_cast<size_t>(i) * w + j] =
+          0.5 * (op->mask[static_cast<size_t>(i) * w + j] +
+                 op->mask[static_cast<size_t>((h - i) % h) * w + (w - j) % w]);
+  std::vector<float> mf(op->mask, op->mask + cnt), sf(sym.begin(), sym.end());
+  IDQ_TRY(upload(&ctx->mask_dev[0], op->mask, cnt * 8));
+  IDQ_TRY(upload(&ctx->mask_dev[1], mf.data(), cnt * 4));
+  if (op->kind == IDQ_OP_MRI) {
+    IDQ_TRY(upload(&ctx->msym_dev[0], sym.data(), cnt * 8));
+    IDQ_TRY(upload(&ctx->msym_dev[1], sf.data(), cnt * 4));
+  }
+  return IDQ_OK;
+}
+
 template <class F>
 int guarded(F&& f) {
   try {
@@ -963,6 +1289,25 @@ int set_device(const idq_ctx* ctx) {
 }
 
 }  // namespace
+}  // namespace idq
+
+namespace idq {
+// Entry points of the training loop (train.hip) into the solver and the backward.
+int solve_internal(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, int c, int h,
+                   int w, int dtype, const idq_solve_opts* o, idq_solve_info* info,
+                   hipStream_t s) {
+  return solve_impl(ctx, y, x0, x_out, n, c, h, w, dtype, o, info, s);
+}
+int backward_internal(idq_ctx* ctx, const void* xbar, const void* y, const void* v, void* dtheta,
+                      double* dlambda, int n, int c, int h, int w, int dtype,
+                      const idq_bwd_opts* o, idq_bwd_info* info, hipStream_t s) {
+  return backward_impl(ctx, xbar, y, v, dtheta, dlambda, n, c, h, w, dtype, o, info, s);
+}
+int repack_weights(idq_ctx* ctx) { return pack_weights(ctx); }
+int dot_batch(idq_ctx* ctx, const void* a, const void* b, long long count, int dtype, double* out,
+              hipStream_t s) {
+  return dot(ctx, a, b, count, dtype, out, s);
+}
 }  // namespace idq
 
 using namespace idq;
@@ -1033,7 +1378,20 @@ int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, in
       ctx->params.assign(net->params, net->params + total);
     }
     ctx->op_kind = op->kind;
-    if (op->kind != IDQ_OP_IDENTITY) {
+    if (op->kind == IDQ_OP_INPAINT || op->kind == IDQ_OP_MRI) {
+      int rc = upload_mask(ctx, op);
+      if (rc < 0) {
+        free_operator(ctx);
+        delete ctx;
+        return rc;
+      }
+    } else if (op->kind == IDQ_OP_RICIAN) {
+      if (!(op->sigma > 0.0) || !std::isfinite(op->sigma)) {
+        delete ctx;
+        return fail(IDQ_E_INVAL, "the Rician term needs sigma > 0");
+      }
+      ctx->sigma = op->sigma;
+    } else if (op->kind != IDQ_OP_IDENTITY) {
       if (op->kind != IDQ_OP_BLUR_CIRC && op->kind != IDQ_OP_TANH_BLUR) {
         delete ctx;
         return fail(IDQ_E_INVAL, "bad operator kind");
@@ -1056,6 +1414,7 @@ int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, in
       int rc = pack_weights(ctx);
       if (rc < 0) {
         free_layers(ctx);
+        free_operator(ctx);
         delete ctx;
         return rc;
       }
@@ -1116,6 +1475,7 @@ int idq_destroy(idq_ctx* ctx) {
   (void)hipDeviceSynchronize();
   ctx->prof.release();
   free_layers(ctx);
+  free_operator(ctx);
   ctx->ws.release();
   if (ctx->host_gate) (void)hipHostFree(ctx->host_gate);
   delete ctx;
@@ -1147,8 +1507,18 @@ int idq_apply_A(idq_ctx* ctx, const void* x, void* Ax, int n, int c, int h, int 
     IDQ_TRY(set_device(ctx));
     IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (ctx->op_kind == IDQ_OP_IDENTITY)
-      return copy_state(x, Ax, static_cast<size_t>(n) * g.per * elem_size(dtype), s);
+    switch (ctx->op_kind) {
+      case IDQ_OP_IDENTITY:
+        return copy_state(x, Ax, static_cast<size_t>(n) * g.per * elem_size(dtype), s);
+      case IDQ_OP_RICIAN:
+        return fail(IDQ_E_UNSUPPORTED, "the Rician model has no forward operator");
+      case IDQ_OP_INPAINT:
+        return datafit(ctx, g, dtype, D_MASK_APPLY, x, nullptr, nullptr, Ax, 0.0, s);
+      case IDQ_OP_MRI:
+        return mri_forward(ctx, g, dtype, x, Ax, s);
+      default:
+        break;
+    }
     StencilArgs a = stencil_base(ctx, g, nullptr);
     a.in0 = x;
     a.out = Ax;
@@ -1167,7 +1537,18 @@ int idq_apply_AT(idq_ctx* ctx, const void* x, const void* v, void* out, int n, i
     IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t sbytes = static_cast<size_t>(n) * g.per * elem_size(dtype);
-    if (ctx->op_kind == IDQ_OP_IDENTITY) return copy_state(v, out, sbytes, s);
+    switch (ctx->op_kind) {
+      case IDQ_OP_IDENTITY:
+        return copy_state(v, out, sbytes, s);
+      case IDQ_OP_RICIAN:
+        return fail(IDQ_E_UNSUPPORTED, "the Rician model has no forward operator");
+      case IDQ_OP_INPAINT:
+        return datafit(ctx, g, dtype, D_MASK_APPLY, v, nullptr, nullptr, out, 0.0, s);
+      case IDQ_OP_MRI:
+        return mri_adjoint(ctx, g, dtype, v, out, s);
+      default:
+        break;
+    }
     const void* src = v;
     if (ctx->op_kind == IDQ_OP_TANH_BLUR) {
       if (!x) return fail(IDQ_E_INVAL, "the tanh-blur adjoint needs the linearisation point x");
@@ -1223,6 +1604,25 @@ int idq_grad_reg(idq_ctx* ctx, const void* x, void* grad, double* g_val, int n, 
       IDQ_HIP(hipStreamSynchronize(s));
     }
     return IDQ_OK;
+  });
+}
+
+int idq_prox_data(idq_ctx* ctx, const void* v, const void* y, double tau, void* out, int n, int c,
+                  int h, int w, int dtype, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !v || !y || !out) return fail(IDQ_E_INVAL, "null argument");
+    if (dtype != IDQ_F64 && dtype != IDQ_F32) return fail(IDQ_E_INVAL, "bad dtype");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(IDQ_E_INVAL, "tau must be positive");
+    if (!has_prox(ctx->op_kind))
+      return fail(IDQ_E_UNSUPPORTED, "this data term has no closed-form proximal step");
+    Geometry g;
+    IDQ_TRY(set_device(ctx));
+    IDQ_TRY(check_shape(ctx, n, c, h, w, &g));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* aty = nullptr;
+    if (ctx->op_kind == IDQ_OP_BLUR_CIRC || ctx->op_kind == IDQ_OP_MRI)
+      IDQ_TRY(data_aty(ctx, g, dtype, y, &aty, s));
+    return prox_apply(ctx, g, dtype, v, nullptr, 0.0, y, aty, tau, out, s);
   });
 }
 

@@ -12,6 +12,8 @@ namespace idq {
 enum Slot {
   W_X0, W_X1, W_Z, W_GF, W_S, W_Q, W_R, W_RD, W_T, W_HG, W_HF, W_V, W_W, W_U, W_UP, W_UN,
   W_PART, W_STATE, W_GATE, W_BETA, W_SCAL, W_WGPART, W_TMP0, W_TMP1, W_HIST, W_ZSUM, W_XHAT,
+  W_CPLX, W_ATY, W_PROX,             // FFT work buffer, A^T y, proximal-step output
+  W_PW, W_TRV, W_TRD,                // adjoint J_P w; training: dL/dx_hat, x_hat - x*
   W_H0,                              // W_H0 + l     : h_{l+1}         (l < L-1)
   W_HD0 = W_H0 + IDQ_MAX_LAYERS,     // W_HD0 + l    : h'_{l+1}
   W_DL0 = W_HD0 + IDQ_MAX_LAYERS,    // W_DL0 + l    : delta_{l+1}
@@ -83,6 +85,15 @@ struct idq_ctx {
   int op_kind = IDQ_OP_IDENTITY, kh = 0, kw = 0;
   double gain = 2.0;
   std::vector<double> taps;
+  // pixel (inpainting) or k-space (MRI) mask, mh x mw, on the device in float64
+  // [IDQ_F64] and float32 [IDQ_F32]; for MRI also the symmetrised mask M_s
+  int mh = 0, mw = 0;
+  void* mask_dev[2] = {};
+  void* msym_dev[2] = {};
+  double sigma = 0.0;          // Rician sigma_y
+  // |k^|^2 of the blur on a spec_h x spec_w grid (Fourier proximal step)
+  void* spec_dev[2] = {};
+  int spec_h[2] = {}, spec_w[2] = {};
   idq::Workspace ws;
   int* host_gate = nullptr;  // pinned, for polling
   int host_gate_cap = 0;
@@ -97,4 +108,15 @@ StencilArgs stencil_base(const idq_ctx* ctx, const Geometry& g, const int* gate)
 // Resolves the device address of the fixed scratch array of the
 // allocation-free entry points on the current device (noalloc.hip).
 int noalloc_init_device(int device);
+// The solver, the backward, the weight packing and a float64 batch dot product
+// (api.hip), for the training loop (train.hip).
+int solve_internal(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, int c, int h,
+                   int w, int dtype, const idq_solve_opts* o, idq_solve_info* info,
+                   hipStream_t s);
+int backward_internal(idq_ctx* ctx, const void* xbar, const void* y, const void* v, void* dtheta,
+                      double* dlambda, int n, int c, int h, int w, int dtype,
+                      const idq_bwd_opts* o, idq_bwd_info* info, hipStream_t s);
+int repack_weights(idq_ctx* ctx);
+int dot_batch(idq_ctx* ctx, const void* a, const void* b, long long count, int dtype, double* out,
+              hipStream_t s);
 }  // namespace idq

@@ -443,9 +443,12 @@ __global__ __launch_bounds__(kBlock) void update_kernel(UpdateArgs a) {
   double s1 = 0.0, s0 = 0.0, nf = 0.0;
   for (long long i = lo + threadIdx.x; i < hi; i += kBlock) {
     const T xv = x[i];
-    const T g = gf ? gf[i] : p[i] - y[i];
-    const T qv = q ? q[i] : T(0);
-    const T v = z[i] - tau * (g + lam * qv);
+    T v = z[i];
+    if (!a.given) {
+      const T g = gf ? gf[i] : p[i] - y[i];
+      const T qv = q ? q[i] : T(0);
+      v -= tau * (g + lam * qv);
+    }
     xn[i] = v;
     const double d = static_cast<double>(v) - static_cast<double>(xv);
     s1 += d * d;
@@ -536,7 +539,9 @@ __global__ __launch_bounds__(kBlock) void update_f4_kernel(UpdateArgs a) {
       if (i < hi) {
         xv[u] = x[i];
         zv[u] = z[i];
-        if (gf) {
+        if (a.given) {
+          gv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else if (gf) {
           gv[u] = gf[i];
         } else {
           const float4 pv = p[i], yv = y[i];

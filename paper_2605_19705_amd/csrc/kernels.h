@@ -143,6 +143,8 @@ struct UpdateArgs {
   int run_mask;        // update image i iff (1 << gate[i]) & run_mask
   double* partials;    // [n][nblk][3]
   int nblk;
+  int given;           // 1: xn = z (the step was formed elsewhere, e.g. a proximal
+                       //    step); gf, p, y, q, tau unused
 };
 int launch_update(const UpdateArgs& a, int dtype, hipStream_t s);
 
@@ -193,6 +195,68 @@ int launch_scale_by(const void* a, void* out, long long count, const double* sca
 // out = alpha * a + beta * b + gamma * c (c nullable)
 int launch_axpbypcz(double alpha, const void* a, double beta, const void* b, double gamma,
                     const void* c, void* out, long long count, int dtype, hipStream_t s);
+
+// ---- pixelwise data terms (inpainting mask, Rician likelihood) -------------
+enum DatafitMode {
+  D_MASK_APPLY = 0,    // out = M . x
+  D_MASK_GRAD = 1,     // out = M (x - y)
+  D_MASK_PROX = 2,     // out = (u + tau M y) / (1 + tau M), u = x + a1 v (v nullable),
+                       // M = 1 where the mask is null (identity operator)
+  D_RICIAN_GRAD = 3,   // out = x / s^2 - (y / s^2) B(x y / s^2),  B = I_1 / I_0
+  D_RICIAN_HESS = 4,   // out = (1 / s^2 - (y / s^2)^2 B'(x y / s^2)) v
+  D_RICIAN_RATIO = 5,  // out = B(x)
+};
+struct DatafitArgs {
+  int mode;
+  long long count;     // elements of x / y / v / out
+  long long plane;     // mask elements (h * w); the mask of element i is mask[i % plane]
+  const void* x;
+  const void* y;
+  const void* v;
+  const void* mask;    // h x w of the element type (mask modes)
+  void* out;
+  double inv_s2;       // 1 / sigma_y^2 (Rician modes)
+  double tau;          // prox step
+  double a1;           // D_MASK_PROX: weight of v in the prox operand
+};
+int launch_datafit(const DatafitArgs& a, int dtype, hipStream_t s);
+
+// ---- 2-D DFT of image planes (k_fft.hip) ------------------------------------
+constexpr int kFftMax = 1024;
+enum FftDir { R_FWD = 0, R_INV = 1 };
+enum FftColMode { C_FWD_MUL_INV = 0, C_FWD_MUL = 1, C_MUL_INV = 2 };
+enum FftMult { M_MUL = 0, M_PROX = 1 };
+struct FftArgs {
+  int NP, H, W;                 // planes of H x W (powers of two, 4..kFftMax)
+  int logh, logw;               // set by the launchers
+  int rows_per_block, cols_per_block;  // set by the launchers
+  // forward rows: real operand in0 + a1 in1 + a2 in2 (in1, in2 nullable)
+  const void* in0;
+  const void* in1;
+  const void* in2;
+  double a1, a2;
+  void* cbuf;                   // complex NP x H x W work buffer (interleaved re, im)
+  const void* cin;              // complex k-space operand of C_MUL_INV
+  void* cout;                   // complex k-space output of C_FWD_MUL
+  const void* mult;             // H x W real multiplier (nullable => 1)
+  int mult_mode;                // M_MUL: scale * mult, M_PROX: scale / (1 + tau mult)
+  double tau, scale;
+  // inverse rows: out = scale_r * Re(row) + b0 * e0 (e0 nullable)
+  void* out;
+  const void* e0;
+  double b0;
+  double scale_r;
+};
+bool fft_supported(int h, int w);
+int launch_fft_rows(FftArgs a, int dir, int dtype, hipStream_t s);
+int launch_fft_cols(FftArgs a, int mode, int dtype, hipStream_t s);
+struct BlurTaps {
+  int kh, kw;
+  double k[81];
+};
+// out[u * w + v] = |k^(u, v)|^2 of the centred taps on an h x w grid
+int launch_blur_spectrum(void* out, int h, int w, const double* taps_host, int kh, int kw,
+                         int dtype, hipStream_t s);
 
 // ---- weight gradient:  dW[co][ci][tap] += scale * sum_p G[p][co] A[p+off][ci] ---
 struct WgradArgs {

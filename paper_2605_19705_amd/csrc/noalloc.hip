@@ -56,6 +56,20 @@ extern "C" int idq_grad_data_noalloc(idq_ctx* ctx, const void* x, const void* y,
     const long long cnt = static_cast<long long>(n) * g.per;
     if (ctx->op_kind == IDQ_OP_IDENTITY)  // grad f = x - y: no intermediate image
       return launch_axpbypcz(1.0, x, -1.0, y, 0.0, nullptr, grad, cnt, dtype, s);
+    if (ctx->op_kind == IDQ_OP_INPAINT || ctx->op_kind == IDQ_OP_RICIAN) {  // pixelwise
+      DatafitArgs d{};
+      d.mode = ctx->op_kind == IDQ_OP_INPAINT ? D_MASK_GRAD : D_RICIAN_GRAD;
+      d.count = cnt;
+      d.plane = static_cast<long long>(h) * w;
+      d.x = x;
+      d.y = y;
+      d.mask = ctx->mask_dev[dtype == IDQ_F64 ? 0 : 1];
+      d.out = grad;
+      d.inv_s2 = ctx->sigma > 0.0 ? 1.0 / (ctx->sigma * ctx->sigma) : 0.0;
+      return launch_datafit(d, dtype, s);
+    }
+    if (ctx->op_kind != IDQ_OP_BLUR_CIRC && ctx->op_kind != IDQ_OP_TANH_BLUR)
+      return fail(IDQ_E_UNSUPPORTED, "idq_grad_data_noalloc: operator without a stencil gradient");
     const size_t bytes = static_cast<size_t>(cnt) * elem_size(dtype);
     if (bytes > static_cast<size_t>(IDQ_NOALLOC_SCRATCH_BYTES))
       return fail(IDQ_E_INVAL, "idq_grad_data_noalloc: " + std::to_string(bytes) +

@@ -44,7 +44,8 @@ def test_version_and_defaults_without_gpu():
 
 
 STRUCTS = {"NetDesc": "idq_net_desc", "OpDesc": "idq_op_desc", "SolveOpts": "idq_solve_opts",
-           "SolveInfo": "idq_solve_info", "BwdOpts": "idq_bwd_opts", "BwdInfo": "idq_bwd_info"}
+           "SolveInfo": "idq_solve_info", "BwdOpts": "idq_bwd_opts", "BwdInfo": "idq_bwd_info",
+           "TrainOpts": "idq_train_opts"}
 
 
 def test_struct_layouts_match_the_header(tmp_path):
