@@ -20,8 +20,10 @@ Two arms are timed:
 Inside the timed region one launch in five of each 64->64 conv class carries
 HIP events (its device time feeds the roofline figures).  After it: one solve
 with every kernel class timed, the tanh-blur workload (16x3x128x128, fp32), the
-4x3x512x512 batch from y, zero and the warm start, and the float64 oracle on
-the host.  Prints one JSON line (value = headline images/s).
+4x3x512x512 batch from y, zero and the warm start, the i-DEQ-P inpainting,
+Rician and i-DEQ-P MRI workloads (8 images of 256x256), training epochs of
+Alg. 1, and the float64 oracle on the host.  Prints one JSON line (value =
+headline images/s).
 """
 import argparse
 import json
@@ -173,6 +175,116 @@ def also_measured(torch, poll, ws, head_ctx=None, head_y=None, head_tau=None):
     return out
 
 
+# Algorithmic bytes per pixel (float32) of one data-term call of the workloads
+# below: the MRI gradient F^H M_s F z - A^T y (forward rows: z in, complex out;
+# columns: complex in and out; inverse rows: complex and A^T y in, real out),
+# the MRI proximal step (the same with z, the regularizer gradient and A^T y
+# read by the forward rows), the inpainting proximal step (z, the regularizer
+# gradient and y in, the result out; the mask is shared by the 3 channels) and
+# the Rician gradient (x and y in, the gradient out).
+DATA_TERM_BYTES_PER_PX = {"mri_grad": 44.0, "mri_prox": 48.0, "inpaint_prox": 16.0 + 4.0 / 3,
+                          "rician_grad": 12.0}
+
+
+def paper_workloads(torch, poll):
+    """The paper's other data terms on 8 synthetic 256^2 images, each solved to
+    rel 1e-4 in float32 and bf16 -> split-bf16 -> float32 (1 warm-up and 2 timed
+    solves per arm), with the data term's device time and bandwidth from one
+    more solve with every kernel class timed; and one training epoch of Alg. 1
+    (16 pairs of 3 x 128^2, K = 100, JFB and implicit)."""
+    import numpy as np
+    import synth
+    from paper_2605_19705_amd import IDQ, Trainer
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def tau_for(ctx, x0, y, lam):
+        v0 = torch.from_numpy(synth.random_field(12345, tuple(x0.shape))).float().to(dev)
+        return 0.9 / ctx.lipschitz(x0, y, v0, lam=lam, iters=30, conv_prec="f32")
+
+    def run(name, ctx, y, x0, lam, beta, proximal, term, px):
+        tau = tau_for(ctx, x0, y, lam)
+        res = {"tau": tau, "lambda": lam, "beta": beta}
+        kw = dict(beta=beta, tau=tau, lam=lam, tol=1e-4, max_iter=3000, poll_every=poll,
+                  proximal=proximal, x0=x0)
+        for arm, extra in (("f32", dict(conv_prec="f32")),
+                           ("bf16_split_f32", dict(conv_prec="bf16", refine_prec="bf16x3",
+                                                   switch_tol=2e-3, switch_patience=5))):
+            r = time_arm(torch, ctx, y, 2, 1, check=False, **kw, **extra)
+            res[arm] = {"images_per_s": y.shape[0] * len(r["step_s"]) / r["total_s"],
+                        "ms_per_solve": 1e3 * r["total_s"] / len(r["step_s"]),
+                        "iters_per_image": r["iters"][-1], "status": r["status"][-1]}
+        cb = class_breakdown(torch, ctx, y, conv_prec="f32", **kw)["stencil"]
+        if cb["launches"]:
+            t = cb["ms"] / cb["launches"]
+            byt = DATA_TERM_BYTES_PER_PX[term] * px
+            res["data_term"] = {"call": term, "calls_one_solve": cb["launches"],
+                                "avg_us": 1e3 * t, "algorithmic_bytes": byt,
+                                "achieved_GBps": byt / (t * 1e-3) / 1e9,
+                                "frac_of_hbm": byt / (t * 1e-3) / 8e12}
+        out[name] = res
+
+    log("bench: i-DEQ-P inpainting (8x3x256x256, 50% pixels, noise 5/255)")
+    n, h, w = 8, 256, 256
+    xt, nz = synth.make_batch(31, n, 3, h, w)
+    m = synth.pixel_mask(31, h, w, 0.5)
+    ctx = IDQ(synth.he_normal_net(synth.net_channels("rgb64"), 0), op_kind="inpaint", mask=m,
+              device=0)
+    y = (ctx.apply_A(torch.from_numpy(xt).float().to(dev)) +
+         5.0 / 255.0 * torch.from_numpy(nz).float().to(dev)).contiguous()
+    run("inpaint_8x3x256_ideq_p", ctx, y, y, 0.83, 0.8, True, "inpaint_prox", n * 3 * h * w)
+    del ctx, y
+
+    log("bench: Rician denoising (8x3x256x256, sigma 25.5/255)")
+    s = 25.5 / 255.0
+    xt, nz = synth.make_batch(33, n, 3, h, w)
+    ni = synth.random_field(330, xt.shape)
+    yr = np.sqrt((xt + s * nz) ** 2 + (s * ni) ** 2)
+    ctx = IDQ(synth.he_normal_net(synth.net_channels("rgb64"), 0), op_kind="rician", sigma=s,
+              device=0)
+    y = torch.from_numpy(yr).float().to(dev).contiguous()
+    run("rician_8x3x256", ctx, y, y, 6.0, 0.8, False, "rician_grad", n * 3 * h * w)
+    del ctx, y
+
+    log("bench: i-DEQ-P MRI x8 (8x1x256x256 k-space, noise 1/255)")
+    xt, nz = synth.make_batch(32, n, 1, h, w)
+    mk = synth.cartesian_mask(32, h, w, accel=8)
+    ctx = IDQ(synth.he_normal_net(synth.net_channels("gray16"), 0), op_kind="mri", mask=mk,
+              device=0)
+    ni = synth.random_field(320, xt.shape)
+    yk = ctx.apply_A(torch.from_numpy(xt).float().to(dev))
+    noise = torch.complex(torch.from_numpy(nz).float(), torch.from_numpy(ni).float()).to(dev)
+    y = (yk + (1.0 / 255.0) * torch.from_numpy(mk).float().to(dev) * noise).contiguous()
+    x0 = ctx.apply_AT(y)
+    run("mri_8x1x256_ideq_p", ctx, y, x0, 0.65, 0.8, True, "mri_prox", n * h * w)
+    del ctx, y, x0
+
+    log("bench: training epochs of Alg. 1 (16x3x128x128 deblurring pairs, K = 100)")
+    xt, nz = synth.make_batch(4, 16, 3, 128, 128)
+    taps = synth.gaussian_taps(9, 1.6)
+    ctx = IDQ(synth.he_normal_net(synth.net_channels("rgb64"), 0), op_kind="blur", taps=taps,
+              device=0)
+    Xs = torch.from_numpy(xt).float().to(dev)
+    Y = (ctx.apply_A(Xs) + 0.01 * torch.from_numpy(nz).float().to(dev)).contiguous()
+    tau = tau_for(ctx, Y, Y, 1.0)
+    tr_out = {"pairs": 16, "K": 100, "tau": tau}
+    for mode, adj in (("jfb", 0), ("implicit", 20)):
+        tr = Trainer(ctx, 1.0)
+        kw = dict(K=100, beta=0.5, tau=tau, mode=mode, lr_theta=1e-4, lr_lambda=1e-3,
+                  adjoint_max_iter=adj, adjoint_tol=0.0)
+        tr.epoch(Y, Xs, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = [tr.epoch(Y, Xs, **kw) for _ in range(2)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 2
+        tr_out[mode] = {"s_per_epoch": dt, "pairs_per_s": 16 / dt, "adjoint_iters": adj,
+                        "loss": losses}
+        tr.close()
+    out["training_epoch_16x3x128_f32"] = tr_out
+    return out
+
+
 def class_breakdown(torch, ctx, y, **kw):
     """Device time per kernel class of one more solve (outside the timed region:
     timing every class adds an event pair to each launch)."""
@@ -253,6 +365,8 @@ def main():
                          "region (each timed launch holds the queue for its event packets)")
     ap.add_argument("--no-also", action="store_true",
                     help="skip the tanh-blur and 512^2 warm-start measurements")
+    ap.add_argument("--no-paper-workloads", action="store_true",
+                    help="skip the inpainting, Rician, MRI and training measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB device-to-device (a plain copy "
                          "kernel of known size, for scaling hardware byte counters)")
@@ -354,6 +468,8 @@ def main():
     phases = class_breakdown(torch, ctx, y, **head_kw)
 
     also = None if args.no_also else also_measured(torch, args.poll, ws, ctx, y, tau)
+    if also is not None and not args.no_paper_workloads:
+        also.update(paper_workloads(torch, args.poll))
 
     cpu = None
     if not args.no_cpu_baseline:
