@@ -976,6 +976,7 @@ int launch_axpbypcz(double alpha, const void* a, double beta, const void* b, dou
 }
 
 int launch_wgrad(const WgradArgs& a, int prec, hipStream_t s) {
+  if (wgrad_mfma_supported(a, prec)) return launch_wgrad_mfma(a, s);
   const int nslots = a.CO * a.CI * 9 + (a.with_bias ? a.CO : 0);
   dim3 grid((nslots + kBlock - 1) / kBlock, a.nchunk);
   if (prec == PREC_F64)
