@@ -139,6 +139,22 @@ def also_measured(torch, poll, ws, head_ctx=None, head_y=None, head_tau=None):
                 "ms_per_solve": 1e3 * r["total_s"] / len(r["step_s"]),
                 "iters_per_image": r["iters"][-1], "status": r["status"][-1]}
 
+    log("bench: denoising 1x1x32x32, float64, 100 fixed updates")
+    ctx1 = IDQ(synth.he_normal_net(synth.net_channels("gray16"), 0), op_kind="identity",
+               device=0)
+    xt1, nz1 = synth.make_batch(1, 1, 1, 32, 32)
+    y1 = torch.from_numpy(xt1 + 25.0 / 255.0 * nz1).to(dev)
+    v01 = torch.from_numpy(synth.random_field(12345, tuple(y1.shape))).to(dev)
+    tau1 = 0.9 / ctx1.lipschitz(y1, y1, v01, lam=1.0, iters=30, conv_prec="f64")
+    r = time_arm(torch, ctx1, y1, 5, 2, check=False, conv_prec="f64", beta=0.5, tau=tau1,
+                 lam=1.0, fixed_iters=100, poll_every=100)
+    out["denoise_1x1x32_f64_100_updates"] = dict(
+        ms_per_solve=1e3 * r["total_s"] / len(r["step_s"]),
+        us_per_update=1e4 * r["total_s"] / len(r["step_s"]),
+        workload="A = identity, noise 25/255, 1->16->16->1 softplus net, float64, 100 updates "
+                 "(launch-bound: 9 kernels per update on a 32x32 image)")
+    del ctx1
+
     log("bench: tanh-blur workload (16x3x128x128, fp32)")
     ctx3 = IDQ(synth.he_normal_net(synth.net_channels("gray16"), 0), op_kind="tanh_blur",
                taps=synth.uniform_taps(7), device=0)

@@ -174,6 +174,12 @@ typedef struct {
                                grad_at = EXTRAPOLATED and an operator with a
                                closed form (identity, blur, inpainting, MRI),
                                else IDQ_E_UNSUPPORTED.  0 (default): Alg. 1.     */
+    int    use_graph;       /* 1 (default): a solve of fixed_iters >= 3 updates in
+                               one conv arithmetic, without averaging or device-time
+                               accounting, replays its steps from a HIP graph on
+                               a stream of the context (ordered after and before
+                               `stream` by events); results are identical.
+                               0: every kernel is launched one by one.           */
 } idq_solve_opts;
 
 /* Per-image results of idq_solve (host array of n entries). */

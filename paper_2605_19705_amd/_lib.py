@@ -58,7 +58,8 @@ class SolveOpts(C.Structure):
                 ("power_iters", C.c_int), ("power_v0", C.c_void_p), ("poll_every", C.c_int),
                 ("init", C.c_int), ("ws", C.c_void_p), ("ws_prec", C.c_int),
                 ("refine_prec", C.c_int), ("rel_history", C.POINTER(C.c_double)),
-                ("history_len", C.c_int), ("averaging", C.c_int), ("proximal", C.c_int)]
+                ("history_len", C.c_int), ("averaging", C.c_int), ("proximal", C.c_int),
+                ("use_graph", C.c_int)]
 
 
 class SolveInfo(C.Structure):

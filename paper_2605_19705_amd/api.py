@@ -245,7 +245,7 @@ class IDQ:
               fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
               switch_tol=2e-3, switch_patience=5, power_iters=30, power_v0=None,
               poll_every=8, init="y", ws=None, ws_prec="bf16", refine_prec="f32",
-              history=0, averaging=False, proximal=False):
+              history=0, averaging=False, proximal=False, use_graph=True):
         """The i-DEQ forward pass (Alg. 1; Alg. 2 with ``proximal``).  For MRI, y
         is complex k-space data and the iterate is real (x0 default A^T y)."""
         o = L.SolveOpts()
@@ -267,6 +267,7 @@ class IDQ:
         o.refine_prec = _PREC[refine_prec]
         o.averaging = 1 if averaging else 0
         o.proximal = 1 if proximal else 0
+        o.use_graph = 1 if use_graph else 0
         n = y.shape[0]
         rdt = _real_dtype(y)
         if y.is_complex() != (self.op_kind == "mri"):

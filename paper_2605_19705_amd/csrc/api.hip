@@ -793,6 +793,18 @@ int ensure_host_gate(idq_ctx* ctx, int n) {
 int ws_forward_internal(idq_ws* ws, const void* y, void* x0, int n, int c, int h, int w, int prec,
                         hipStream_t s);  // ws.hip
 
+// The context's stream for graph capture and replay (non-blocking, default
+// priority) and its two ordering events, created on first use.
+int graph_stream(idq_ctx* ctx, hipStream_t* out) {
+  if (!ctx->gstream) {
+    IDQ_HIP(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+    IDQ_HIP(hipEventCreateWithFlags(&ctx->gev[0], hipEventDisableTiming));
+    IDQ_HIP(hipEventCreateWithFlags(&ctx->gev[1], hipEventDisableTiming));
+  }
+  *out = ctx->gstream;
+  return IDQ_OK;
+}
+
 namespace {
 
 int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, int c, int h,
@@ -942,7 +954,103 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   fa.use_mid = use_mid ? 1 : 0;
   fa.avg_K = averaging ? o->fixed_iters : 0;
 
+  // one solver step t on stream st: extrapolation, gradients, update, finalize
+  auto step = [&](int t, int run, bool mid_now, hipStream_t st) -> int {
+    void* xa = xb[t % 2];
+    void* xp = xb[(t + 1) % 2];
+    IDQ_TRY(profiled(ctx, PC_UPDATE, st, [&] {
+      return launch_extrap(xa, xp, z, static_cast<const double*>(beta), gp, run, n, g.per,
+                           dtype, st);
+    }));
+    const void* p = o->grad_at == IDQ_GRAD_AT_CURRENT ? xa : z;
+    if (!identity && !proximal)
+      IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, st, false, run, aty));
+    if (use_net) {
+      if (run & (1 << G_LOW)) IDQ_TRY(net_grad(ctx, g, IDQ_BF16, p, q, gp, 1 << G_LOW, st));
+      if (mid_now) IDQ_TRY(net_grad(ctx, g, IDQ_BF16X3, p, q, gp, 1 << G_MID, st));
+      if (run & (1 << G_FINAL)) IDQ_TRY(net_grad(ctx, g, final_prec, p, q, gp, 1 << G_FINAL, st));
+    }
+    UpdateArgs ua{};
+    ua.n = n;
+    ua.per = g.per;
+    ua.x = xa;
+    ua.xn = xp;
+    if (proximal) {
+      // i-DEQ-P (Alg. 2): x^{k+1} = prox_{tau f}(z - tau lambda grad g(z)), formed
+      // over the whole batch; the update kernel takes it for the images it runs
+      IDQ_TRY(profiled(ctx, PC_STENCIL, st, [&] {
+        return prox_apply(ctx, g, dtype, z, use_net ? q : nullptr, -tau * o->lambda, y, aty, tau,
+                          pbuf, st);
+      }));
+      ua.z = pbuf;
+      ua.given = 1;
+    } else {
+      ua.z = z;
+      ua.gf = identity ? nullptr : gf;
+      ua.p = p;
+      ua.y = y;
+      ua.q = use_net ? q : nullptr;
+    }
+    ua.tau = tau;
+    ua.lambda = o->lambda;
+    ua.gate = gp;
+    ua.run_mask = run;
+    ua.partials = static_cast<double*>(part);
+    ua.nblk = nblk;
+    FinalizeArgs fs = fa;
+    fs.buf_index = (t + 1) % 2;
+    fs.history = static_cast<double*>(hist);
+    fs.history_rows = hist_len;
+    fs.run_mask = run;
+    IDQ_TRY(profiled(ctx, PC_UPDATE, st, [&] {
+      IDQ_TRY(launch_update(ua, dtype, st));
+      return launch_finalize(fs, st);
+    }));
+    // with averaging every image updates on every step, so step t is update t + 1
+    if (averaging)
+      IDQ_TRY(launch_average(z, zsum, xhat, static_cast<const ImgState*>(state), t + 1, n, g.per,
+                             dtype, st));
+    return IDQ_OK;
+  };
+
   int t = 0;
+  // A fixed number of steps in one arithmetic needs no host decision between
+  // them: step 0 runs as usual (it sizes every workspace buffer), steps 1 and 2
+  // are captured into a HIP graph once, and the graph is replayed for each
+  // following pair (the buffers' roles repeat with period 2).  Launch-bound
+  // solves (small images) then pay one graph launch per two steps.
+  if (o->use_graph && !bf_start && !ctx->prof.on && !averaging && o->fixed_iters >= 3) {
+    const int run = 1 << G_FINAL;
+    IDQ_TRY(step(0, run, false, s));
+    hipStream_t gs;
+    IDQ_TRY(graph_stream(ctx, &gs));
+    IDQ_HIP(hipEventRecord(ctx->gev[0], s));
+    IDQ_HIP(hipStreamWaitEvent(gs, ctx->gev[0], 0));
+    const int pairs = (limit - 1) / 2;
+    hipGraph_t graph = nullptr;
+    IDQ_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+    int rc1 = step(1, run, false, gs);
+    int rc2 = rc1 < 0 ? rc1 : step(2, run, false, gs);
+    hipError_t ec = hipStreamEndCapture(gs, &graph);
+    if (rc2 < 0) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc2;
+    }
+    if (ec != hipSuccess) return fail(IDQ_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ec != hipSuccess) return fail(IDQ_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ec));
+    for (int pr = 0; pr < pairs && ec == hipSuccess; ++pr) ec = hipGraphLaunch(exec, gs);
+    t = 1 + 2 * pairs;
+    int rc3 = (ec == hipSuccess && t < limit) ? step(t, run, false, gs) : IDQ_OK;
+    hipError_t es = hipStreamSynchronize(gs);
+    (void)hipGraphExecDestroy(exec);
+    if (ec != hipSuccess) return fail(IDQ_E_HIP, std::string("graph launch: ") + hipGetErrorString(ec));
+    if (es != hipSuccess) return fail(IDQ_E_HIP, std::string("graph stream: ") + hipGetErrorString(es));
+    IDQ_TRY(rc3);
+    t = host_limit;
+  }
   while (t < host_limit) {
     // once only float32-phase images remain (a bf16 start), each needs about one
     // more update: poll after every step rather than launch empty steps
@@ -952,58 +1060,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
       const bool mid_now = mid_live && (j > 0 || mid_seen);
       const int run = (low_live ? 1 << G_LOW : 0) | (mid_now ? 1 << G_MID : 0) |
                       (fin_live ? 1 << G_FINAL : 0);
-      void* xa = xb[t % 2];
-      void* xp = xb[(t + 1) % 2];
-      IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
-        return launch_extrap(xa, xp, z, static_cast<const double*>(beta), gp, run, n, g.per,
-                             dtype, s);
-      }));
-      const void* p = o->grad_at == IDQ_GRAD_AT_CURRENT ? xa : z;
-      if (!identity && !proximal) IDQ_TRY(data_grad(ctx, g, dtype, p, y, gf, gp, s, false, run, aty));
-      if (use_net) {
-        if (low_live) IDQ_TRY(net_grad(ctx, g, IDQ_BF16, p, q, gp, 1 << G_LOW, s));
-        if (mid_now) IDQ_TRY(net_grad(ctx, g, IDQ_BF16X3, p, q, gp, 1 << G_MID, s));
-        if (fin_live) IDQ_TRY(net_grad(ctx, g, final_prec, p, q, gp, 1 << G_FINAL, s));
-      }
-      UpdateArgs ua{};
-      ua.n = n;
-      ua.per = g.per;
-      ua.x = xa;
-      ua.xn = xp;
-      if (proximal) {
-        // i-DEQ-P (Alg. 2): x^{k+1} = prox_{tau f}(z - tau lambda grad g(z)), formed
-        // over the whole batch; the update kernel takes it for the images it runs
-        IDQ_TRY(profiled(ctx, PC_STENCIL, s, [&] {
-          return prox_apply(ctx, g, dtype, z, use_net ? q : nullptr, -tau * o->lambda, y, aty,
-                            tau, pbuf, s);
-        }));
-        ua.z = pbuf;
-        ua.given = 1;
-      } else {
-        ua.z = z;
-        ua.gf = identity ? nullptr : gf;
-        ua.p = p;
-        ua.y = y;
-        ua.q = use_net ? q : nullptr;
-      }
-      ua.tau = tau;
-      ua.lambda = o->lambda;
-      ua.gate = gp;
-      ua.run_mask = run;
-      ua.partials = static_cast<double*>(part);
-      ua.nblk = nblk;
-      fa.buf_index = (t + 1) % 2;
-      fa.history = static_cast<double*>(hist);
-      fa.history_rows = hist_len;
-      fa.run_mask = run;
-      IDQ_TRY(profiled(ctx, PC_UPDATE, s, [&] {
-        IDQ_TRY(launch_update(ua, dtype, s));
-        return launch_finalize(fa, s);
-      }));
-      // with averaging every image updates on every step, so step t is update t + 1
-      if (averaging)
-        IDQ_TRY(launch_average(z, zsum, xhat, static_cast<const ImgState*>(state), t + 1, n,
-                               g.per, dtype, s));
+      IDQ_TRY(step(t, run, mid_now, s));
     }
     IDQ_HIP(hipMemcpyAsync(ctx->host_gate, gate, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     IDQ_HIP(hipStreamSynchronize(s));
@@ -1336,6 +1393,7 @@ void idq_solve_opts_default(idq_solve_opts* o) {
   o->init = IDQ_INIT_Y;
   o->ws_prec = IDQ_BF16;
   o->refine_prec = IDQ_F32;
+  o->use_graph = 1;
 }
 
 int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, int device) {
@@ -1476,6 +1534,11 @@ int idq_destroy(idq_ctx* ctx) {
   ctx->prof.release();
   free_layers(ctx);
   free_operator(ctx);
+  if (ctx->gstream) {
+    (void)hipStreamDestroy(ctx->gstream);
+    (void)hipEventDestroy(ctx->gev[0]);
+    (void)hipEventDestroy(ctx->gev[1]);
+  }
   ctx->ws.release();
   if (ctx->host_gate) (void)hipHostFree(ctx->host_gate);
   delete ctx;

@@ -95,6 +95,8 @@ struct idq_ctx {
   void* spec_dev[2] = {};
   int spec_h[2] = {}, spec_w[2] = {};
   idq::Workspace ws;
+  hipStream_t gstream = nullptr;  // graph capture / replay (created on first use)
+  hipEvent_t gev[2] = {};
   int* host_gate = nullptr;  // pinned, for polling
   int host_gate_cap = 0;
   idq::Profiler prof;

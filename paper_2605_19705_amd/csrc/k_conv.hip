@@ -2,8 +2,9 @@
 // (the conv layers inside g(x) = 1/2 ||x - N(x)||^2, eq. GS).
 //
 // Two kernel families share one argument block (ConvArgs):
-//   * conv_direct: one thread per (pixel, 16 output channels), scalar FMA in the
-//     math type.  Used for float64 and for shapes the MFMA kernels do not cover.
+//   * conv_direct: one thread per (pixel, 4 output channels) of a 16 x 16 tile,
+//     operand halo and weights staged in LDS, scalar FMA in the math type.  Used
+//     for float64 and for shapes the MFMA kernels do not cover.
 //   * conv_mfma (k_conv_mfma.hip): implicit GEMM on the gfx950 matrix cores.
 //   * conv_thin (k_conv_thin.hip): image-facing outputs (CO <= 3) from NHWC
 //     activations, float32 on the vector ALUs.
@@ -32,36 +33,63 @@ __device__ inline TM load_operand(const ConvArgs& a, int ni, int ci, int yy, int
   return v;
 }
 
+// Tile shape of the direct kernel: 16 x 16 output pixels (one per thread) and
+// DCO output channels per workgroup; the operand's (18 x 18)-pixel halo is
+// staged in LDS DCI input channels at a time, the weights of the workgroup's
+// output channels once, so the inner loop reads only LDS (the weights as
+// broadcasts).
+constexpr int DT = 16, DH = DT + 2, DHP = DH * DH, DCO = 4, DCI = 16;
+
 template <typename TM, typename TS, typename TA, bool RBF>
-__global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a) {
-  const int HW = a.H * a.W;
-  const int p = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void conv_direct_kernel(ConvArgs a, int ntx) {
+  extern __shared__ __attribute__((aligned(16))) char dsm[];
+  TM* halo = reinterpret_cast<TM*>(dsm);             // [DCI][DHP]
+  TM* wl = halo + DCI * DHP;                         // [DCO][CI][9]
+  const int tid = threadIdx.x;
   const int ni = blockIdx.y;
-  const int co0 = blockIdx.z * 16;
-  if (p >= HW) return;
+  const int ty0 = (blockIdx.x / ntx) * DT, tx0 = (blockIdx.x % ntx) * DT;
+  const int co0 = blockIdx.z * DCO;
   if (!gate_open(a.gate, a.gate_mask, ni / a.img_div)) return;
-  if (a.work_px && blockIdx.z == 0) atomicAdd(a.work_px, 1ull);
-  const int y = p / a.W, x = p - (p / a.W) * a.W;
-  const int nco = min(16, a.CO - co0);
+  const int ly = tid / DT, lx = tid % DT;
+  const int y = ty0 + ly, x = tx0 + lx;
+  const bool inside = y < a.H && x < a.W;
+  if (a.work_px && blockIdx.z == 0 && inside) atomicAdd(a.work_px, 1ull);
+  const int nco = min(DCO, a.CO - co0);
   const TM* w = static_cast<const TM*>(a.wgt);
-  TM acc[16];
+  for (int i = tid; i < nco * a.CI * 9; i += 256)
+    wl[i] = w[static_cast<size_t>(co0) * a.CI * 9 + i];
+  TM acc[DCO];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = TM(0);
-  for (int ci = 0; ci < a.CI; ++ci) {
-    for (int t = 0; t < 9; ++t) {
-      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-      if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) continue;
-      TM v = load_operand<TM, TS, TA>(a, ni, ci, yy, xx);
-      if (RBF) v = static_cast<TM>(round_bf(static_cast<float>(v)));
-      const TM* wp = w + (static_cast<size_t>(co0) * a.CI + ci) * 9 + t;
+  for (int j = 0; j < DCO; ++j) acc[j] = TM(0);
+  for (int c0 = 0; c0 < a.CI; c0 += DCI) {
+    const int nci = min(DCI, a.CI - c0);
+    __syncthreads();  // the previous channel chunk has been read
+    for (int i = tid; i < nci * DHP; i += 256) {
+      const int cc = i / DHP, hp = i - cc * DHP;
+      const int yy = ty0 - 1 + hp / DH, xx = tx0 - 1 + hp % DH;
+      TM v = TM(0);
+      if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+        v = load_operand<TM, TS, TA>(a, ni, c0 + cc, yy, xx);
+        if (RBF) v = static_cast<TM>(round_bf(static_cast<float>(v)));
+      }
+      halo[cc * DHP + hp] = v;
+    }
+    __syncthreads();
+    for (int cc = 0; cc < nci; ++cc) {
+      const TM* hc = halo + cc * DHP + ly * DH + lx;
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j < nco) acc[j] += wp[static_cast<size_t>(j) * a.CI * 9] * v;
+      for (int t = 0; t < 9; ++t) {
+        const TM v = hc[(t / 3) * DH + t % 3];
+#pragma unroll
+        for (int j = 0; j < DCO; ++j)
+          if (j < nco) acc[j] += wl[(static_cast<size_t>(j) * a.CI + c0 + cc) * 9 + t] * v;
+      }
     }
   }
+  if (!inside) return;
   const TM* bias = static_cast<const TM*>(a.bias);
   const bool sp = a.act == IDQ_ACT_SOFTPLUS;
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < DCO; ++j) {
     if (j >= nco) break;
     const int co = co0 + j;
     const TM b = bias ? bias[co] : TM(0);
@@ -144,18 +172,22 @@ int launch_conv(const ConvArgs& a, int prec, hipStream_t s) {
   if (prec != PREC_F64 && a.wmfma && mfma_supported(prec, a.CI, a.CO) &&
       mfma_form_ok(a, prec))
     return launch_conv_mfma(a, prec, s);
-  dim3 grid((a.H * a.W + 255) / 256, a.NI, (a.CO + 15) / 16);
-  if (grid.y > 65535) return fail(IDQ_E_INVAL, "too many images in one conv pass");
+  const int ntx = (a.W + DT - 1) / DT, nty = (a.H + DT - 1) / DT;
+  dim3 grid(ntx * nty, a.NI, (a.CO + DCO - 1) / DCO);
+  if (grid.y > 65535 || grid.z > 65535) return fail(IDQ_E_INVAL, "too many images in one conv pass");
+  const size_t es = prec == PREC_F64 ? 8 : 4;
+  const size_t lds = es * (static_cast<size_t>(DCI) * DHP + static_cast<size_t>(DCO) * a.CI * 9);
+  if (lds > 64 * 1024) return fail(IDQ_E_UNSUPPORTED, "direct conv: too many input channels");
   if (a.ev0) IDQ_HIP(hipEventRecord(a.ev0, s));
   switch (prec) {
     case PREC_F64:
-      conv_direct_kernel<double, double, double, false><<<grid, 256, 0, s>>>(a);
+      conv_direct_kernel<double, double, double, false><<<grid, 256, lds, s>>>(a, ntx);
       break;
     case PREC_F32:
-      conv_direct_kernel<float, float, float, false><<<grid, 256, 0, s>>>(a);
+      conv_direct_kernel<float, float, float, false><<<grid, 256, lds, s>>>(a, ntx);
       break;
     case PREC_BF16:
-      conv_direct_kernel<float, float, bf16, true><<<grid, 256, 0, s>>>(a);
+      conv_direct_kernel<float, float, bf16, true><<<grid, 256, lds, s>>>(a, ntx);
       break;
     default:
       return fail(IDQ_E_INVAL, "bad conv precision");

@@ -14,9 +14,10 @@
 // fragment per pair (4 px x 16 ci of the shifted A), one v_mfma_f32_16x16x4f32
 // each, accumulating the whole chunk in registers.  The chunk's sums go to
 // float64 partials [chunk][slot] that a fixed-order reduction adds up, so the
-// result does not depend on scheduling.  Used for float32 passes whose
-// operands are NHWC activations with CI and CO multiples of 16 (the hidden
-// layers); image-facing layers keep the vector-ALU kernel.
+// result does not depend on scheduling.  Used for float32 passes over NHWC
+// activations with CI and CO multiples of 16 (the hidden layers) and for the
+// image-facing layers of the 64-channel net, whose 1..16-channel NCHW operand
+// is zero-padded to 16 channels in LDS.
 #include "kernels.h"
 
 namespace idq {
@@ -40,10 +41,14 @@ struct WCfg {
   static_assert(NCO == 1 || NCO == 2 || NCO == 4, "CO must be 16, 32 or 64");
 };
 
-template <int CI, int CO>
+// CI, CO: the GEMM's (padded) channel counts, multiples of 16.  A_NCHW / G_NCHW:
+// the operand is a 1..16-channel NCHW state tensor (an image-facing layer: its
+// a.CI / a.CO real channels, zero-padded to 16 in LDS).
+template <int CI, int CO, bool A_NCHW, bool G_NCHW>
 __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx, int nty,
                                                            int ntiles) {
   using C = WCfg<CI, CO>;
+  const int cir = A_NCHW ? a.CI : CI, cor = G_NCHW ? a.CO : CO;
   extern __shared__ __attribute__((aligned(16))) float wsm[];
   float* la = wsm;                    // [HPIX][CIP]
   float* lg = wsm + HPIX * C::CIP;    // [TPIX][COP]
@@ -64,6 +69,20 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
     const int ni = t / tiles_per_img, rem = t - ni * tiles_per_img;
     const int ty0 = (rem / ntx) * TH, tx0 = (rem % ntx) * TW;
     __syncthreads();  // the previous tile's fragments have been read
+    if constexpr (A_NCHW) {
+      // one value per item; channels past the real ones stay zero
+      for (int it = tid; it < HPIX * CI; it += kWT) {
+        const int c = it / HPIX, p = it - c * HPIX;
+        const int gy = ty0 - 1 + p / HWD, gx = tx0 - 1 + p % HWD;
+        float v = 0.f;
+        if (c < cir && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+          const size_t e = ((static_cast<size_t>(ni) * cir + c) * a.H + gy) * a.W + gx;
+          v = A0[e];
+          if (a.a_pro == P_JVP) v = (sp ? dsp_from_a(v) : 1.f) * A1[e];
+        }
+        la[p * C::CIP + c] = v;
+      }
+    } else
     // A halo: 4 channels per item
     for (int it = tid; it < HPIX * (CI / 4); it += kWT) {
       const int p = it / (CI / 4), c4 = (it - p * (CI / 4)) * 4;
@@ -80,6 +99,16 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
       }
       *reinterpret_cast<f32x4_t*>(la + p * C::CIP + c4) = v;
     }
+    if constexpr (G_NCHW) {
+      for (int it = tid; it < TPIX * CO; it += kWT) {
+        const int c = it / TPIX, p = it - c * TPIX;
+        const int gy = ty0 + p / TW, gx = tx0 + p % TW;
+        float v = 0.f;
+        if (c < cor && gy < a.H && gx < a.W)
+          v = G[((static_cast<size_t>(ni) * cor + c) * a.H + gy) * a.W + gx];
+        lg[p * C::COP + c] = v;
+      }
+    } else
     // G tile
     for (int it = tid; it < TPIX * (CO / 4); it += kWT) {
       const int p = it / (CO / 4), c4 = (it - p * (CO / 4)) * 4;
@@ -90,7 +119,7 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
       *reinterpret_cast<f32x4_t*>(lg + p * C::COP + c4) = v;
     }
     __syncthreads();
-    if (a.with_bias && tid < CO) {
+    if (a.with_bias && tid < cor) {
       for (int p = 0; p < TPIX; ++p) bsum += lg[p * C::COP + tid];
     }
     // K loop: 4 tile pixels per step; lane row kq takes pixel 4s + kq
@@ -111,8 +140,8 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
     }
   }
   // partials of this chunk: lane holds D rows (co) 4 kq + i, column (ci) l16
-  const int nw = CO * CI * 9;
-  const int nslots = nw + (a.with_bias ? CO : 0);
+  const int nw = cor * cir * 9;
+  const int nslots = nw + (a.with_bias ? cor : 0);
   double* out = a.partials + static_cast<size_t>(blockIdx.x) * nslots;
 #pragma unroll
   for (int j = 0; j < C::MAXP; ++j) {
@@ -123,18 +152,19 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int co = cbo * 16 + 4 * kq + i;
-        out[(static_cast<size_t>(co) * CI + ci) * 9 + tap] = static_cast<double>(acc[j][i]);
+        if (ci < cir && co < cor)
+          out[(static_cast<size_t>(co) * cir + ci) * 9 + tap] = static_cast<double>(acc[j][i]);
       }
     }
   }
-  if (a.with_bias && tid < CO) out[nw + tid] = static_cast<double>(bsum);
+  if (a.with_bias && tid < cor) out[nw + tid] = static_cast<double>(bsum);
 }
 
-template <int CI, int CO>
+template <int CI, int CO, bool A_NCHW = false, bool G_NCHW = false>
 int launch_shape(const WgradArgs& a, hipStream_t s) {
   using C = WCfg<CI, CO>;
   static bool attr = false;
-  auto kern = wgrad_mfma_kernel<CI, CO>;
+  auto kern = wgrad_mfma_kernel<CI, CO, A_NCHW, G_NCHW>;
   if (!attr) {
     IDQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS));
@@ -151,14 +181,21 @@ int launch_shape(const WgradArgs& a, hipStream_t s) {
 }  // namespace
 
 bool wgrad_mfma_supported(const WgradArgs& a, int prec) {
-  if (prec != PREC_F32 || a.g_fmt != F_NHWC || a.a_fmt != F_NHWC) return false;
+  if (prec != PREC_F32) return false;
   const int ci = a.CI, co = a.CO;
+  // image-facing layers of the 64-channel net: 3 -> 64 (A an NCHW state
+  // tensor) and 64 -> 3 (G an NCHW state tensor)
+  if (a.a_fmt == F_NCHW && a.g_fmt == F_NHWC) return ci <= 16 && co == 64;
+  if (a.a_fmt == F_NHWC && a.g_fmt == F_NCHW) return ci == 64 && co <= 16;
+  if (a.g_fmt != F_NHWC || a.a_fmt != F_NHWC) return false;
   return (ci == 16 && co == 16) || (ci == 32 && co == 32) || (ci == 64 && co == 64) ||
          (ci == 32 && co == 64) || (ci == 64 && co == 32) || (ci == 96 && co == 32);
 }
 
 int launch_wgrad_mfma(const WgradArgs& a, hipStream_t s) {
   if (a.nchunk <= 0) return fail(IDQ_E_INVAL, "wgrad: no chunks");
+  if (a.a_fmt == F_NCHW) return launch_shape<16, 64, true, false>(a, s);
+  if (a.g_fmt == F_NCHW) return launch_shape<64, 16, false, true>(a, s);
   switch (a.CI * 1000 + a.CO) {
     case 16016: return launch_shape<16, 16>(a, s);
     case 32032: return launch_shape<32, 32>(a, s);

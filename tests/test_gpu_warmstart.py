@@ -19,8 +19,10 @@ pytestmark = pytest.mark.gpu
 # accumulate in float64); through 9 convs the relative error stays ~1e-6.
 TOL_F32 = 2e-5
 # bf16 path: activations and weights round to 8 mantissa bits (2^-9 relative
-# each), float32 accumulation; errors from 9 layers add up to ~1e-2.
-TOL_BF16 = 5e-2
+# each), float32 accumulation.  Measured on MI355X: 7.8e-3 for the network
+# output, 4.5e-3 .. 7.9e-3 for the layers' gradients; the bound is the 2e-2
+# relative tolerance of bf16 results.
+TOL_BF16 = 2e-2
 
 
 def _layers(seed=3):
@@ -74,6 +76,7 @@ def test_forward_matches_oracle(prec, tol):
     assert np.all(np.isfinite(x0))
     # compare the network output W_phi(y) = x0 - y
     err = _rel(x0 - y32, ref - y32)
+    print(f"warm-start forward {prec}: relative error of W_phi(y) {err:.3e}", flush=True)
     assert err < tol, (prec, err)
 
 
@@ -96,6 +99,8 @@ def test_loss_gradient_matches_oracle(prec, tol):
         gw = g[off:off + dW.size]
         gb = g[off + dW.size:off + dW.size + db.size]
         off += dW.size + db.size
+        print(f"warm-start gradient {prec} layer {l}: W {_rel(gw, dW.ravel()):.3e} "
+              f"b {_rel(gb, db.ravel()):.3e}", flush=True)
         assert _rel(gw, dW.ravel()) < tol, (prec, l, "W", _rel(gw, dW.ravel()))
         assert _rel(gb, db.ravel()) < tol, (prec, l, "b", _rel(gb, db.ravel()))
     assert off == g.size
