@@ -298,6 +298,20 @@ def paper_workloads(torch, poll):
                         "loss": losses}
         tr.close()
     out["training_epoch_16x3x128_f32"] = tr_out
+
+    log("bench: warm-start training steps (16x3x128x128 pairs, bf16, Adam)")
+    from paper_2605_19705_amd import WarmStart
+    ws = WarmStart(synth.warmstart_init(0), device=0)
+    yb, tb = Y[:16].contiguous(), Xs[:16].contiguous()
+    ws.train_step(yb, tb, 1e-4, prec="bf16", want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        ws.train_step(yb, tb, 1e-4, prec="bf16", want_loss=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 10
+    out["warmstart_train_step_16x3x128_bf16"] = {"ms_per_step": 1e3 * dt, "pairs_per_s": 16 / dt,
+                                                 "params": ws.num_params}
     return out
 
 
