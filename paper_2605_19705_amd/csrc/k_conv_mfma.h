@@ -486,7 +486,7 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfm
   // shapes (split, and float32 from 3 or 64 channels), whose matrix-core work
   // per tile is short next to the HBM latency of the next halo and whose
   // second buffer fits the register budget
-  constexpr int DEPTH = C::W8 ? 2 : 1;
+  constexpr int DEPTH = (C::W8 && !C::SPLIT) ? 2 : 1;
   Prefetch<C, PRO> pf, pf2;
   int t1 = DEPTH > 1 ? next_open(t) : 0;
   issue(pf, t);
@@ -659,6 +659,63 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfm
           }
         }
       };
+      if constexpr (C::SPLIT) {
+        // split operands: the input rows (hi and lo parts) of the next (dx, chunk)
+        // step are read from LDS before this step's matrix-core groups, so their
+        // latency hides behind 36 MFMAs instead of stalling the first group
+        constexpr int NR = RW + 2;
+        u32x4_t bh[2][NR], bl[2][NR];
+        auto load_rows = [&](u32x4_t* h, u32x4_t* l, int dxc) {
+          const int dx = dxc / C::CPT, c = dxc % C::CPT;
+          const int coff = (c * C::KC + g * C::V) * C::ES;
+#pragma unroll
+          for (int ir = 0; ir < NR; ++ir) {
+            const int pix = (wv * RW + ir) * HW_ + c16 + dx;
+            h[ir] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + coff);
+            l[ir] = *reinterpret_cast<const u32x4_t*>(lin + pix * C::PIXB + C::LO_OFF + coff);
+          }
+        };
+        // one (dx, chunk) step on the rows in (h, l) while (hn, ln) receive the next
+        // step's rows; steps run in pairs so that both buffers are fixed registers
+        auto split_step = [&](int dxc, const u32x4_t* h, const u32x4_t* l, u32x4_t* hn,
+                              u32x4_t* ln) {
+          if (dxc + 1 < 3 * C::CPT) load_rows(hn, ln, dxc + 1);
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            if (dy < 2)
+              load_af(afn, aln, dxc, dy + 1);
+            else if (dxc + 1 < 3 * C::CPT)
+              load_af(afn, aln, dxc + 1, 0);
+            // small terms first (lo*hi, hi*lo, then hi*hi), each term over all
+            // accumulators before the next
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], l[r + dy]);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], alc[j], h[r + dy]);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], h[r + dy]);
+#pragma unroll
+            for (int j = 0; j < NJW; ++j) {
+              afc[j] = afn[j];
+              alc[j] = aln[j];
+            }
+          }
+        };
+        constexpr int NS = 3 * C::CPT;
+        load_rows(bh[0], bl[0], 0);
+#pragma unroll 1
+        for (int dxc = 0; dxc + 1 < NS; dxc += 2) {
+          split_step(dxc, bh[0], bl[0], bh[1], bl[1]);
+          split_step(dxc + 1, bh[1], bl[1], bh[0], bl[0]);
+        }
+        if constexpr (NS % 2 == 1) split_step(NS - 1, bh[0], bl[0], bh[1], bl[1]);
+      } else {
       // the first PEEL steps (unrolled: their piece indices are constants) carry
       // the previous tile's epilogue pieces; the rest run as a plain loop
       constexpr int PEEL = PIPE ? ((NPIECE + 2) / 3 < 3 * C::CPT ? (NPIECE + 2) / 3 : 3 * C::CPT) : 0;
@@ -666,6 +723,7 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfm
       for (int dxc = 0; dxc < PEEL; ++dxc) dxc_step(dxc, std::true_type{});
 #pragma unroll C::RUNROLL
       for (int dxc = PEEL; dxc < 3 * C::CPT; ++dxc) dxc_step(dxc, std::false_type{});
+      }
     } else {
 #pragma unroll C::UNROLL
       for (int ch = 0; ch < C::NCH; ++ch) {
