@@ -42,6 +42,7 @@ extern "C" {
 #define IDQ_E_HIP          -3   /* HIP runtime error (message has the reason)  */
 #define IDQ_E_NONFINITE    -4   /* a non-finite iterate was produced           */
 #define IDQ_E_UNSUPPORTED  -5   /* option combination not implemented          */
+#define IDQ_E_DIVERGED     -6   /* an image's iterate passed diverge_ratio x ||x^0|| */
 
 /* ---- element / arithmetic types ---------------------------------------- */
 #define IDQ_F64   0
@@ -85,6 +86,7 @@ extern "C" {
 #define IDQ_ST_MAXITER     1
 #define IDQ_ST_FIXED       2
 #define IDQ_ST_NONFINITE  -4
+#define IDQ_ST_DIVERGED   -6   /* iterate norm above diverge_ratio: stopped     */
 
 typedef struct idq_ctx idq_ctx;
 typedef struct idq_ws idq_ws;
@@ -174,6 +176,19 @@ typedef struct {
                                grad_at = EXTRAPOLATED and an operator with a
                                closed form (identity, blur, inpainting, MRI),
                                else IDQ_E_UNSUPPORTED.  0 (default): Alg. 1.     */
+    double diverge_ratio;   /* an image whose iterate norm ||x^k|| exceeds this
+                               times ||x^0|| (||x^1|| when x^0 = 0) stops with
+                               IDQ_ST_DIVERGED (default 1e6; <= 0: off).  With tau
+                               too large for the curvature the iterates grow
+                               geometrically while the relative step stays
+                               bounded, so the norm is what is tested.          */
+    const void* x_prev;     /* device, nullable: x^{-1} of a resumed iteration; the
+                               first step then extrapolates with beta (restart
+                               counters start from zero).  NULL: x^{-1} = x^0.     */
+    void*  x_prev_out;      /* device, nullable: receives each image's iterate
+                               before x_out (x_out itself where the last update
+                               restarted the inertia), so that (x_out, x_prev_out)
+                               as (x0, x_prev) continues the iteration exactly.   */
     int    use_graph;       /* 1 (default): a solve of fixed_iters >= 3 updates in
                                one conv arithmetic, without averaging or device-time
                                accounting, replays its steps from a HIP graph on

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libidq.so")
 
 IDQ_OK, IDQ_W_MAXITER = 0, 1
 IDQ_E_INVAL, IDQ_E_NOMEM, IDQ_E_HIP, IDQ_E_NONFINITE, IDQ_E_UNSUPPORTED = -1, -2, -3, -4, -5
+IDQ_E_DIVERGED = -6
 IDQ_F64, IDQ_F32, IDQ_BF16, IDQ_BF16X3 = 0, 1, 2, 3
 IDQ_ACT_SOFTPLUS, IDQ_ACT_IDENTITY = 0, 1
 IDQ_OP_IDENTITY, IDQ_OP_BLUR_CIRC, IDQ_OP_TANH_BLUR = 0, 1, 2
@@ -21,6 +22,7 @@ IDQ_GRAD_AT_EXTRAPOLATED, IDQ_GRAD_AT_CURRENT = 0, 1
 IDQ_INIT_Y, IDQ_INIT_ZERO, IDQ_INIT_WARMSTART = 0, 1, 2
 IDQ_MAX_LAYERS = 8
 IDQ_ST_CONVERGED, IDQ_ST_MAXITER, IDQ_ST_FIXED, IDQ_ST_NONFINITE = 0, 1, 2, -4
+IDQ_ST_DIVERGED = -6
 IDQ_BWD_JFB, IDQ_BWD_IMPLICIT = 0, 1
 IDQ_PROF_ALL = 0x7fffffff
 IDQ_NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -59,6 +61,7 @@ class SolveOpts(C.Structure):
                 ("init", C.c_int), ("ws", C.c_void_p), ("ws_prec", C.c_int),
                 ("refine_prec", C.c_int), ("rel_history", C.POINTER(C.c_double)),
                 ("history_len", C.c_int), ("averaging", C.c_int), ("proximal", C.c_int),
+                ("diverge_ratio", C.c_double), ("x_prev", C.c_void_p), ("x_prev_out", C.c_void_p),
                 ("use_graph", C.c_int)]
 
 

@@ -245,7 +245,8 @@ class IDQ:
               fixed_iters=0, restart_B=0.0, grad_at="extrapolated", conv_prec=None,
               switch_tol=2e-3, switch_patience=5, power_iters=30, power_v0=None,
               poll_every=8, init="y", ws=None, ws_prec="bf16", refine_prec="f32",
-              history=0, averaging=False, proximal=False, use_graph=True):
+              history=0, averaging=False, proximal=False, use_graph=True, diverge_ratio=1e6,
+              x_prev=None, x_prev_out=None):
         """The i-DEQ forward pass (Alg. 1; Alg. 2 with ``proximal``).  For MRI, y
         is complex k-space data and the iterate is real (x0 default A^T y)."""
         o = L.SolveOpts()
@@ -268,6 +269,9 @@ class IDQ:
         o.averaging = 1 if averaging else 0
         o.proximal = 1 if proximal else 0
         o.use_graph = 1 if use_graph else 0
+        o.diverge_ratio = float(diverge_ratio)
+        o.x_prev = _ptr(x_prev).value if x_prev is not None else None
+        o.x_prev_out = _ptr(x_prev_out).value if x_prev_out is not None else None
         n = y.shape[0]
         rdt = _real_dtype(y)
         if y.is_complex() != (self.op_kind == "mri"):
@@ -281,7 +285,7 @@ class IDQ:
         x = out if out is not None else torch.empty(y.shape, device=y.device, dtype=rdt)
         code = L.lib().idq_solve(self._h, _ptr(y), _ptr(x0), _ptr(x), *_shape4(y), _dtype_code(x),
                                  C.byref(o), info, _stream())
-        L.check(code, allow=(L.IDQ_OK, L.IDQ_W_MAXITER, L.IDQ_E_NONFINITE))
+        L.check(code, allow=(L.IDQ_OK, L.IDQ_W_MAXITER, L.IDQ_E_NONFINITE, L.IDQ_E_DIVERGED))
         res = SolveResult(iters=np.array([i.iters for i in info]),
                           iters_low=np.array([i.iters_low for i in info]),
                           iters_mid=np.array([i.iters_mid for i in info]),

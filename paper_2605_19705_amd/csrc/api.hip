@@ -875,7 +875,10 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   } else {
     return fail(IDQ_E_INVAL, "bad init");
   }
-  IDQ_TRY(copy_state(xb[0], xb[1], sbytes, s));
+  if (o->x_prev)
+    IDQ_TRY(copy_state(o->x_prev, xb[1], sbytes, s));
+  else
+    IDQ_TRY(copy_state(xb[0], xb[1], sbytes, s));
   // averaging: running float64 sum of the z^k and the averaged output (x^0
   // until the window's first step)
   double* zsum = nullptr;
@@ -912,7 +915,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
     st.avg_best = INFINITY;
   }
   std::vector<int> hg(n, first_gate);
-  std::vector<double> hb(n, 0.0);
+  std::vector<double> hb(n, o->x_prev ? o->beta : 0.0);  // x^{-1} = x^0: no first inertia
   IDQ_HIP(hipMemcpyAsync(state, hs.data(), sizeof(ImgState) * n, hipMemcpyHostToDevice, s));
   IDQ_HIP(hipMemcpyAsync(gate, hg.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
   IDQ_HIP(hipMemcpyAsync(beta, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
@@ -953,6 +956,7 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   fa.fixed_iters = o->fixed_iters;
   fa.use_mid = use_mid ? 1 : 0;
   fa.avg_K = averaging ? o->fixed_iters : 0;
+  fa.diverge_ratio = o->diverge_ratio;
 
   // one solver step t on stream st: extrapolation, gradients, update, finalize
   auto step = [&](int t, int run, bool mid_now, hipStream_t st) -> int {
@@ -1083,6 +1087,9 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
   else
     IDQ_TRY(launch_gather_result(xb[0], xb[1], x_out, static_cast<const ImgState*>(state), n,
                                  g.per, dtype, s));
+  if (o->x_prev_out)
+    IDQ_TRY(launch_gather_result(xb[0], xb[1], o->x_prev_out, static_cast<const ImgState*>(state),
+                                 n, g.per, dtype, s, 1));
   IDQ_HIP(hipMemcpyAsync(hs.data(), state, sizeof(ImgState) * n, hipMemcpyDeviceToHost, s));
   if (hist_len)
     IDQ_HIP(hipMemcpyAsync(o->rel_history, hist, sizeof(double) * n * hist_len,
@@ -1102,6 +1109,12 @@ int solve_impl(idq_ctx* ctx, const void* y, const void* x0, void* x_out, int n, 
         set_error("image " + std::to_string(i) + " produced a non-finite iterate after " +
                   std::to_string(hs[i].it) + " updates");
       rc = IDQ_E_NONFINITE;
+    } else if (hs[i].status == IDQ_ST_DIVERGED) {
+      if (rc >= 0)
+        set_error("image " + std::to_string(i) + " diverged: its iterate norm passed " +
+                  std::to_string(o->diverge_ratio) + " times the initial one after " +
+                  std::to_string(hs[i].it) + " updates");
+      if (rc >= 0) rc = IDQ_E_DIVERGED;
     } else if (hs[i].status == IDQ_ST_MAXITER && rc == IDQ_OK) {
       set_error("image " + std::to_string(i) + " reached max_iter");
       rc = IDQ_W_MAXITER;
@@ -1394,6 +1407,7 @@ void idq_solve_opts_default(idq_solve_opts* o) {
   o->ws_prec = IDQ_BF16;
   o->refine_prec = IDQ_F32;
   o->use_graph = 1;
+  o->diverge_ratio = 1e6;
 }
 
 int idq_create(idq_ctx** out, const idq_net_desc* net, const idq_op_desc* op, int device) {

@@ -608,6 +608,7 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
       s.avg_snap = k + 1;
     }
   }
+  if (s.it == 0) s.norm0_sq = s0 > 0.0 ? s0 : s1;   // ||x^0||^2, or ||x^1||^2 from x^0 = 0
   s.it += 1;
   s.kr += 1;
   s.S += s1;
@@ -617,6 +618,12 @@ __global__ __launch_bounds__(64) void finalize_kernel(FinalizeArgs a) {
   int gate = s.prec;
   if (nf > 0.0 || !isfinite(s1)) {
     s.status = IDQ_ST_NONFINITE;
+    s.done = 1;
+  } else if (a.diverge_ratio > 0.0 && s.norm0_sq > 0.0 &&
+             s0 > a.diverge_ratio * a.diverge_ratio * s.norm0_sq) {
+    // the iterate norm grows geometrically when tau is too large for the
+    // curvature (the relative step itself stays bounded)
+    s.status = IDQ_ST_DIVERGED;
     s.done = 1;
   } else {
     s.beta_eff = a.beta;
@@ -691,10 +698,13 @@ __global__ __launch_bounds__(kBlock) void average_kernel(const T* z, double* zsu
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void gather_kernel(const T* b0, const T* b1, T* out,
-                                                      const ImgState* st, long long per) {
+                                                      const ImgState* st, long long per,
+                                                      int prev) {
   const int img = blockIdx.y;
   const size_t base = static_cast<size_t>(img) * per;
-  const T* src = st[img].last_buf == 0 ? b0 : b1;
+  int which = st[img].last_buf;
+  if (prev && st[img].beta_eff != 0.0) which ^= 1;
+  const T* src = which == 0 ? b0 : b1;
   for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < per;
        i += (long long)gridDim.x * kBlock)
     out[base + i] = src[base + i];
@@ -893,16 +903,16 @@ int launch_finalize(const FinalizeArgs& a, hipStream_t s) {
 }
 
 int launch_gather_result(const void* b0, const void* b1, void* out, const ImgState* st, int n,
-                         long long per, int dtype, hipStream_t s) {
+                         long long per, int dtype, hipStream_t s, int prev) {
   dim3 grid(grid_for(per), n);
   if (dtype == IDQ_F64)
     gather_kernel<double><<<grid, kBlock, 0, s>>>(static_cast<const double*>(b0),
                                                   static_cast<const double*>(b1),
-                                                  static_cast<double*>(out), st, per);
+                                                  static_cast<double*>(out), st, per, prev);
   else
     gather_kernel<float><<<grid, kBlock, 0, s>>>(static_cast<const float*>(b0),
                                                  static_cast<const float*>(b1),
-                                                 static_cast<float*>(out), st, per);
+                                                 static_cast<float*>(out), st, per, prev);
   IDQ_HIP(hipGetLastError());
   return IDQ_OK;
 }

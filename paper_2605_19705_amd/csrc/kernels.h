@@ -155,6 +155,7 @@ struct ImgState {
   int last_buf, it_mid, avg_snap, pad2;
   double S, rel, best_rel, beta_eff;
   double avg_best;      // averaging: smallest ||x^{k+1} - x^k|| over the window
+  double norm0_sq;      // ||x^0||^2 (||x^1||^2 when x^0 = 0), for the blow-up test
 };
 struct FinalizeArgs {
   int n, nblk;
@@ -170,6 +171,7 @@ struct FinalizeArgs {
   double* history;      // nullable: [update][n] relative residuals, `history_rows` rows
   int history_rows;
   int avg_K;            // > 0: averaging step over a run of avg_K updates (Alg. 1)
+  double diverge_ratio; // > 0: ||x^k|| > diverge_ratio * ||x^0|| stops the image (DIVERGED)
 };
 int launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // Averaging step of Alg. 1, after each finalize of a run where every image
@@ -179,9 +181,11 @@ int launch_finalize(const FinalizeArgs& a, hipStream_t s);
 // float64 whatever the dtype.
 int launch_average(const void* z, double* zsum, void* xhat, const ImgState* st, int it_now,
                    int n, long long per, int dtype, hipStream_t s);
-// x_out[img] = bufs[st[img].last_buf][img]
+// x_out[img] = bufs[st[img].last_buf][img]; with `prev` the iterate before it,
+// bufs[1 - last_buf][img], or x_out itself where the last update restarted the
+// inertia (beta_eff = 0), so that (x_out, prev) resumes the iteration exactly
 int launch_gather_result(const void* b0, const void* b1, void* out, const ImgState* st,
-                         int n, long long per, int dtype, hipStream_t s);
+                         int n, long long per, int dtype, hipStream_t s, int prev = 0);
 
 // Batch float64 dot product <a, b> (deterministic two-stage); result in *out.
 int launch_dot(const void* a, const void* b, long long count, int dtype, double* partials,
