@@ -47,12 +47,12 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # pixels per timed launch.  A figure is valid only while the kernel's device
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
-    "conv64_bf16": {"bytes_per_px": 337.16,
-                    "sha256": "0db8ae6212d6309a65e377a64719c181f494b59a176f2ced39b377150e2f7da6",
+    "conv64_bf16": {"bytes_per_px": 336.90,
+                    "sha256": "92248610fb8ea9d2b7ba089b5f0e0e84a817e8ec4db9444850d4db30bac81022",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
-    "conv64_bf16x3": {"bytes_per_px": 673.35,
-                      "sha256": "471cb6a61e3e8ff4c7d805dc150d11d3a07db743571b6870f026514817bb8259",
+    "conv64_bf16x3": {"bytes_per_px": 672.85,
+                      "sha256": "4439c5b94092bdce30056056287084318d9fbfd1a6f585a954a4d86bd6a12a4e",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},
 }
