@@ -822,15 +822,23 @@ __global__ __launch_bounds__(kBlock) void wgrad_kernel(WgradArgs a) {
   a.partials[static_cast<size_t>(blockIdx.y) * nslots + slot] = acc;
 }
 
+// Sum of the chunk partials per slot: a block takes 64 slots; its 4 waves each
+// add every 4th chunk in order, then wave 0 adds the 4 sums in a fixed order,
+// so the result does not depend on scheduling.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void reduce_chunks_kernel(const double* partials, int nchunk,
                                                              int count, double scale, T* out,
                                                              int accumulate) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= count) return;
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += partials[static_cast<size_t>(c) * count + i];
-  const double v = scale * s;
+  if (i < count)
+    for (int c = q; c < nchunk; c += 4) s += partials[static_cast<size_t>(c) * count + i];
+  part[q][lane] = s;
+  __syncthreads();
+  if (q != 0 || i >= count) return;
+  const double v = scale * ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
   out[i] = accumulate ? static_cast<T>(static_cast<double>(out[i]) + v) : static_cast<T>(v);
 }
 
@@ -986,7 +994,7 @@ int launch_axpbypcz(double alpha, const void* a, double beta, const void* b, dou
 }
 
 int launch_wgrad(const WgradArgs& a, int prec, hipStream_t s) {
-  if (wgrad_mfma_supported(a, prec)) return launch_wgrad_mfma(a, s);
+  if (wgrad_mfma_supported(a, prec)) return launch_wgrad_mfma(a, prec, s);
   const int nslots = a.CO * a.CI * 9 + (a.with_bias ? a.CO : 0);
   dim3 grid((nslots + kBlock - 1) / kBlock, a.nchunk);
   if (prec == PREC_F64)
@@ -1001,7 +1009,9 @@ int launch_wgrad(const WgradArgs& a, int prec, hipStream_t s) {
 
 int launch_reduce_chunks(const double* partials, int nchunk, int count, double scale, void* out,
                          int accumulate, int dtype, hipStream_t s) {
-  const int g = (count + kBlock - 1) / kBlock;
+  static_assert(kBlock == 256, "reduce_chunks_kernel takes 4 waves");
+  if (count <= 0) return IDQ_OK;
+  const int g = (count + 63) / 64;
   if (dtype == IDQ_F64)
     reduce_chunks_kernel<double><<<g, kBlock, 0, s>>>(partials, nchunk, count, scale,
                                                       static_cast<double*>(out), accumulate);

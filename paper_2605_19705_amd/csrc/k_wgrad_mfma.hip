@@ -14,10 +14,11 @@
 // fragment per pair (4 px x 16 ci of the shifted A), one v_mfma_f32_16x16x4f32
 // each, accumulating the whole chunk in registers.  The chunk's sums go to
 // float64 partials [chunk][slot] that a fixed-order reduction adds up, so the
-// result does not depend on scheduling.  Used for float32 passes over NHWC
-// activations with CI and CO multiples of 16 (the hidden layers) and for the
-// image-facing layers of the 64-channel net, whose 1..16-channel NCHW operand
-// is zero-padded to 16 channels in LDS.
+// result does not depend on scheduling.  Used for float32 and bf16 passes over
+// NHWC activations with CI and CO multiples of 16 (the hidden layers; bf16
+// values convert exactly to float32 in LDS, so the products are those of the
+// float32 path) and for the image-facing layers of the 32- and 64-channel
+// nets, whose 1..16-channel NCHW operand is zero-padded to 16 channels in LDS.
 #include "kernels.h"
 
 namespace idq {
@@ -41,10 +42,23 @@ struct WCfg {
   static_assert(NCO == 1 || NCO == 2 || NCO == 4, "CO must be 16, 32 or 64");
 };
 
+// 4 consecutive NHWC channels as floats: float32 or bfloat16 storage
+template <bool BF>
+__device__ inline f32x4_t load4(const void* base, size_t e) {
+  if (BF) {
+    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(base) + e);
+    return f32x4_t{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                   __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
+  }
+  return *reinterpret_cast<const f32x4_t*>(static_cast<const float*>(base) + e);
+}
+
 // CI, CO: the GEMM's (padded) channel counts, multiples of 16.  A_NCHW / G_NCHW:
 // the operand is a 1..16-channel NCHW state tensor (an image-facing layer: its
-// a.CI / a.CO real channels, zero-padded to 16 in LDS).
-template <int CI, int CO, bool A_NCHW, bool G_NCHW>
+// a.CI / a.CO real channels, zero-padded to 16 in LDS).  BF: the NHWC
+// activations are bfloat16 (the warm start's bf16 training), converted exactly
+// to float32 in LDS; NCHW state tensors are float32.
+template <int CI, int CO, bool A_NCHW, bool G_NCHW, bool BF>
 __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx, int nty,
                                                            int ntiles) {
   using C = WCfg<CI, CO>;
@@ -59,7 +73,7 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
   const bool sp = a.act == IDQ_ACT_SOFTPLUS;
   const float* G = static_cast<const float*>(a.g);
   const float* A0 = static_cast<const float*>(a.a0);
-  const float* A1 = static_cast<const float*>(a.a1);
+  const float* A1 = static_cast<const float*>(a.a1);   // NCHW operands only
   f32x4_t acc[C::MAXP];
 #pragma unroll
   for (int j = 0; j < C::MAXP; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -90,9 +104,9 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
       f32x4_t v = {0.f, 0.f, 0.f, 0.f};
       if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
         const size_t e = ((static_cast<size_t>(ni) * a.H + gy) * a.W + gx) * CI + c4;
-        v = *reinterpret_cast<const f32x4_t*>(A0 + e);
+        v = load4<BF>(a.a0, e);
         if (a.a_pro == P_JVP) {
-          const f32x4_t d = *reinterpret_cast<const f32x4_t*>(A1 + e);
+          const f32x4_t d = load4<BF>(a.a1, e);
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] = (sp ? dsp_from_a(v[q]) : 1.f) * d[q];
         }
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
       const int gy = ty0 + p / TW, gx = tx0 + p % TW;
       f32x4_t v = {0.f, 0.f, 0.f, 0.f};
       if (gy < a.H && gx < a.W)
-        v = *reinterpret_cast<const f32x4_t*>(G + ((static_cast<size_t>(ni) * a.H + gy) * a.W + gx) * CO + c4);
+        v = load4<BF>(a.g, ((static_cast<size_t>(ni) * a.H + gy) * a.W + gx) * CO + c4);
       *reinterpret_cast<f32x4_t*>(lg + p * C::COP + c4) = v;
     }
     __syncthreads();
@@ -160,11 +174,11 @@ __global__ __launch_bounds__(kWT, 1) void wgrad_mfma_kernel(WgradArgs a, int ntx
   if (a.with_bias && tid < cor) out[nw + tid] = static_cast<double>(bsum);
 }
 
-template <int CI, int CO, bool A_NCHW = false, bool G_NCHW = false>
+template <int CI, int CO, bool A_NCHW = false, bool G_NCHW = false, bool BF = false>
 int launch_shape(const WgradArgs& a, hipStream_t s) {
   using C = WCfg<CI, CO>;
   static bool attr = false;
-  auto kern = wgrad_mfma_kernel<CI, CO, A_NCHW, G_NCHW>;
+  auto kern = wgrad_mfma_kernel<CI, CO, A_NCHW, G_NCHW, BF>;
   if (!attr) {
     IDQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS));
@@ -181,30 +195,41 @@ int launch_shape(const WgradArgs& a, hipStream_t s) {
 }  // namespace
 
 bool wgrad_mfma_supported(const WgradArgs& a, int prec) {
-  if (prec != PREC_F32) return false;
+  if (prec != PREC_F32 && prec != PREC_BF16) return false;
   const int ci = a.CI, co = a.CO;
-  // image-facing layers of the 64-channel net: 3 -> 64 (A an NCHW state
-  // tensor) and 64 -> 3 (G an NCHW state tensor)
-  if (a.a_fmt == F_NCHW && a.g_fmt == F_NHWC) return ci <= 16 && co == 64;
-  if (a.a_fmt == F_NHWC && a.g_fmt == F_NCHW) return ci == 64 && co <= 16;
+  // image-facing layers: A an NCHW state tensor (3 -> 32 / 64), or G one (32 / 64 -> 3)
+  if (a.a_fmt == F_NCHW && a.g_fmt == F_NHWC) return ci <= 16 && (co == 32 || co == 64);
+  if (a.a_fmt == F_NHWC && a.g_fmt == F_NCHW) return (ci == 32 || ci == 64) && co <= 16;
   if (a.g_fmt != F_NHWC || a.a_fmt != F_NHWC) return false;
-  return (ci == 16 && co == 16) || (ci == 32 && co == 32) || (ci == 64 && co == 64) ||
-         (ci == 32 && co == 64) || (ci == 64 && co == 32) || (ci == 96 && co == 32);
+  return (ci == 16 && co == 16 && prec == PREC_F32) || (ci == 32 && co == 32) ||
+         (ci == 64 && co == 64) || (ci == 32 && co == 64) || (ci == 64 && co == 32) ||
+         (ci == 96 && co == 32);
 }
 
-int launch_wgrad_mfma(const WgradArgs& a, hipStream_t s) {
-  if (a.nchunk <= 0) return fail(IDQ_E_INVAL, "wgrad: no chunks");
-  if (a.a_fmt == F_NCHW) return launch_shape<16, 64, true, false>(a, s);
-  if (a.g_fmt == F_NCHW) return launch_shape<64, 16, false, true>(a, s);
+namespace {
+template <bool BF>
+int dispatch(const WgradArgs& a, hipStream_t s) {
+  if (a.a_fmt == F_NCHW)
+    return a.CO == 64 ? launch_shape<16, 64, true, false, BF>(a, s)
+                      : launch_shape<16, 32, true, false, BF>(a, s);
+  if (a.g_fmt == F_NCHW)
+    return a.CI == 64 ? launch_shape<64, 16, false, true, BF>(a, s)
+                      : launch_shape<32, 16, false, true, BF>(a, s);
   switch (a.CI * 1000 + a.CO) {
-    case 16016: return launch_shape<16, 16>(a, s);
-    case 32032: return launch_shape<32, 32>(a, s);
-    case 64064: return launch_shape<64, 64>(a, s);
-    case 32064: return launch_shape<32, 64>(a, s);
-    case 64032: return launch_shape<64, 32>(a, s);
-    case 96032: return launch_shape<96, 32>(a, s);
+    case 16016: return launch_shape<16, 16, false, false, BF>(a, s);
+    case 32032: return launch_shape<32, 32, false, false, BF>(a, s);
+    case 64064: return launch_shape<64, 64, false, false, BF>(a, s);
+    case 32064: return launch_shape<32, 64, false, false, BF>(a, s);
+    case 64032: return launch_shape<64, 32, false, false, BF>(a, s);
+    case 96032: return launch_shape<96, 32, false, false, BF>(a, s);
     default: return fail(IDQ_E_UNSUPPORTED, "wgrad: no matrix-core shape");
   }
+}
+}  // namespace
+
+int launch_wgrad_mfma(const WgradArgs& a, int prec, hipStream_t s) {
+  if (a.nchunk <= 0) return fail(IDQ_E_INVAL, "wgrad: no chunks");
+  return prec == PREC_BF16 ? dispatch<true>(a, s) : dispatch<false>(a, s);
 }
 
 }  // namespace idq

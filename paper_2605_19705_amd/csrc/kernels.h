@@ -275,10 +275,11 @@ struct WgradArgs {
   int with_bias;           // also sum G over pixels into the bias slots
 };
 int launch_wgrad(const WgradArgs& a, int prec, hipStream_t s);
-// float32 matrix-core form for NHWC operands with CI, CO multiples of 16
-// (k_wgrad_mfma.hip); launch_wgrad takes it where supported.
+// float32 matrix-core form (k_wgrad_mfma.hip) for float32 or bf16 NHWC operands
+// with CI, CO multiples of 16 and for the image-facing layers of the 32- and
+// 64-channel nets; launch_wgrad takes it where supported.
 bool wgrad_mfma_supported(const WgradArgs& a, int prec);
-int launch_wgrad_mfma(const WgradArgs& a, hipStream_t s);
+int launch_wgrad_mfma(const WgradArgs& a, int prec, hipStream_t s);
 // out[i] (+)= scale * sum_chunk partials[chunk][i]; out of dtype, i < count
 int launch_reduce_chunks(const double* partials, int nchunk, int count, double scale,
                          void* out, int accumulate, int dtype, hipStream_t s);

@@ -426,7 +426,7 @@ int ws_grad_impl(idq_ws* ws, const void* y, const void* target, int n, int h, in
     const WsLayer& L = ws->L[l];
     const int nslots = L.co * L.ci * 9 + L.co;
     const long long pix = static_cast<long long>(n) * hh * ww;
-    const int nchunk = static_cast<int>(std::max<long long>(1, std::min<long long>(512, pix / 512)));
+    const int nchunk = static_cast<int>(std::max<long long>(1, std::min<long long>(256, pix / 1024)));
     void* wp;
     IDQ_TRY(ws->ws.get(S_WG, static_cast<size_t>(nchunk) * nslots * 8, &wp));
     WgradArgs wa{};
