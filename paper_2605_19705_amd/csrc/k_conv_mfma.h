@@ -686,6 +686,9 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfm
               load_af(afn, aln, dxc, dy + 1);
             else if (dxc + 1 < 3 * C::CPT)
               load_af(afn, aln, dxc + 1, 0);
+            // the scheduler may not sink these reads into the matrix-core group
+            // below: issued here, their latency hides behind its 12 MFMAs
+            __builtin_amdgcn_sched_barrier(0);
             // small terms first (lo*hi, hi*lo, then hi*hi), each term over all
             // accumulators before the next
 #pragma unroll
@@ -700,6 +703,7 @@ __global__ __launch_bounds__((Cfg<PREC, CI, CO, PRO>::THREADS), 1) void conv_mfm
             for (int r = 0; r < RW; ++r)
 #pragma unroll
               for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], h[r + dy]);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < NJW; ++j) {
               afc[j] = afn[j];
