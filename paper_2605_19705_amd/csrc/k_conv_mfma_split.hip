@@ -1,6 +1,7 @@
 // Split-bf16 instantiations of the implicit-GEMM conv (kernel in k_conv_mfma.h):
 // float activations, each operand taken as bf16 hi + lo parts on the matrix cores.
 #include "k_conv_mfma.h"
+#include "k_conv_split64.h"
 
 namespace idq {
 namespace mfma {
@@ -9,6 +10,17 @@ namespace {
 
 template <int CI, int CO>
 int by_epi(const ConvArgs& a, hipStream_t s) {
+  if constexpr (CI == 64) {
+    // channel-half pipelined kernel (k_conv_split64.h)
+    if (split64_fits(a)) {
+      switch (a.epi) {
+        case E_ACT: return launch_split64<CO, E_ACT>(a, s);
+        case E_DELTA: return launch_split64<CO, E_DELTA>(a, s);
+        case E_RAW: return launch_split64<CO, E_RAW>(a, s);
+        default: return fail(IDQ_E_UNSUPPORTED, "no split-bf16 MFMA epilogue of this kind");
+      }
+    }
+  }
   switch (a.epi) {
     case E_ACT: return launch_shape<PREC_SPLIT, CI, CO, P_NONE, E_ACT>(a, s);
     case E_DELTA: return launch_shape<PREC_SPLIT, CI, CO, P_NONE, E_DELTA>(a, s);

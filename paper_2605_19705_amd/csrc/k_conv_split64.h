@@ -1,0 +1,426 @@
+// Split-bf16 3x3 convolution from 64 input channels (to 32 or 64 outputs),
+// software-pipelined over the two halves of the input channels.
+//
+// Same arithmetic as the split form of conv_mfma_kernel (k_conv_mfma.h): float
+// activations and float weights each taken as a bf16 hi part plus the bf16
+// rounding of the remainder, acc += W_lo x_hi + W_hi x_lo + W_hi x_hi on
+// v_mfma_f32_16x16x32_bf16, 32 output channels per workgroup (two workgroups
+// per tile for 64 outputs, on one XCD), the 18 x 18 halo tile and this
+// workgroup's hi and lo weight fragments in LDS (161,856 bytes: one workgroup
+// per compute unit).  4 waves of 4 output rows: one wave per SIMD with the
+// whole register file (the pipeline below holds two accumulator sets, two
+// halo halves and double-buffered fragments), its matrix-core groups of 24
+// MFMAs long enough to cover one group's LDS reads.
+//
+// What differs is the schedule.  The K loop runs channel half 0 (K chunks of
+// input channels 0..31, all 9 taps) and then channel half 1.  Each half reads
+// only its own bytes of every halo pixel, so while the waves run half 0 of
+// tile t, half 1 of the same tile goes from registers into LDS, and while they
+// run half 1, half 0 of the next tile does: the LDS stage overlaps the
+// matrix-core work instead of sitting between tiles, and the LDS footprint
+// stays that of one tile.  The epilogue (SoftPlus or sigma', stores) of tile t
+// is issued in pieces during half 0 of tile t + 1, the halo loads from HBM one
+// half ahead of their LDS stage.  Per wave and (dx, chunk) step the six input
+// rows are read once for the three kernel rows (dy) that use them, a third of
+// them per group during the previous step; weight fragment reads are issued
+// one matrix-core group ahead; MFMAs, LDS and memory operations are
+// interleaved by scheduling-group hints.
+//
+// Waits on the vector memory counter: it retires loads and stores in one
+// count, and a wait for a load while stores are outstanding waits for those
+// stores as well.  So each half first consumes the halo registers loaded a
+// half earlier (one wait, for memory issued at least a half before) and only
+// then issues the next loads; the epilogue's stores sit early in half 0, most
+// of a half before the next such wait.
+#pragma once
+
+#include "k_conv_mfma.h"
+
+namespace idq {
+namespace mfma {
+
+constexpr int kS64Threads = 256;
+
+template <int CO, int EPI>
+__global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a, int ntx,
+                                                                      int nty, int ntiles) {
+  using C = Cfg<PREC_SPLIT, 64, CO, P_NONE>;
+  static_assert(C::NJW == 2 && C::CPT == 2 && C::WLO_LDS && C::LO_OFF == 128 && C::KC == 32,
+                "shape of the channel-half pipeline");
+  static_assert(EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW, "NHWC float outputs");
+  constexpr int NT_ = kS64Threads, RW = TH / (NT_ / 64), NJW = 2, NR = RW + 2;
+  // 16-byte items (4 channels of one pixel) of one channel half, per thread
+  constexpr int HITEMS = NPIX * 8;
+  constexpr int NHI = (HITEMS + NT_ - 1) / NT_;
+  static_assert(NHI > 9 && NHI <= 2 * 9, "items of a half are staged one or two per group");
+  static_assert(RW * NJW % 2 == 0 && RW * NJW / 2 + 1 < 9 && RW % 2 == 0,
+                "epilogue pieces fit half 0");
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  char* lin = smem;
+  const u32x4_t* lw = reinterpret_cast<const u32x4_t*>(smem + C::LDS_IN);
+  const u32x4_t* lwl = lw + C::NCH * NJW * 64;
+  const u32x4_t* gw = static_cast<const u32x4_t*>(a.wmfma);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, c16 = lane & 15;
+  const bool sp = a.act == IDQ_ACT_SOFTPLUS;
+  const int tiles_per_img = ntx * nty;
+  auto open = [&](int tt) {
+    return gate_open_uniform(a.gate, a.gate_mask, (tt / tiles_per_img) / a.img_div);
+  };
+
+  // channel group and tile walk (as in conv_mfma_kernel)
+  int jh = 0, walker = static_cast<int>(blockIdx.x);
+  if (C::CSPLIT > 1) {
+    const int b = static_cast<int>(blockIdx.x);
+    if (gridDim.x % (8 * C::CSPLIT) == 0) {
+      const int grp = b / 8;
+      jh = grp % C::CSPLIT;
+      walker = (grp / C::CSPLIT) * 8 + b % 8;
+    } else {
+      jh = b % C::CSPLIT;
+      walker = b / C::CSPLIT;
+    }
+  }
+  const int tstep = static_cast<int>(gridDim.x) / C::CSPLIT;
+  int t = walker;
+  while (t < ntiles && !open(t)) t += tstep;
+  if (t >= ntiles) return;
+  auto next_open = [&](int tt) {
+    tt += tstep;
+    while (tt < ntiles && !open(tt)) tt += tstep;
+    return tt;
+  };
+
+  // item k of a half: pixel it / 8 of the halo, channels 32 h + 4 (it % 8) ..
+  // + 3, it = tid + 256 k.  Read through a buffer resource over the tile's
+  // image: 32-bit offsets, and an offset outside it (a halo pixel beyond the
+  // image) reads zero
+  const unsigned img_bytes = static_cast<unsigned>(a.H * a.W) * 256u;
+  // (branch-free, so that it can be scheduled among the MFMAs: past the last
+  // tile the resource covers zero bytes and every load reads zero)
+  auto load_half = [&](u32x4_t (&buf)[NHI], int tt, int h, int k0, int k1) {
+    const bool real = tt < ntiles;
+    const int tc = real ? tt : 0;
+    const int ni = tc / tiles_per_img, rem = tc - ni * tiles_per_img;
+    const int ty0 = (rem / ntx) * TH, tx0 = (rem % ntx) * TW;
+    const __amdgpu_buffer_rsrc_t rs = out_rsrc(
+        const_cast<char*>(static_cast<const char*>(a.in0)) + static_cast<size_t>(ni) * img_bytes,
+        real ? img_bytes : 0u);
+#pragma unroll
+    for (int k = k0; k < k1; ++k) {
+      const int it = tid + k * NT_;
+      const int p = it >> 3, q = it & 7;
+      const int ly = p / HW_, lx = p - (p / HW_) * HW_;
+      const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
+      const bool in = it < HITEMS && static_cast<unsigned>(gy) < static_cast<unsigned>(a.H) &&
+                      static_cast<unsigned>(gx) < static_cast<unsigned>(a.W);
+      const unsigned off = in ? static_cast<unsigned>((gy * a.W + gx) * 256 + h * 128 + q * 16)
+                              : kDropOffset;
+      const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off), 0, 0);
+      buf[k] = u32x4_t{v[0], v[1], v[2], v[3]};
+    }
+  };
+  // hi parts and bf16-rounded remainders of item k into the half's LDS bytes
+  auto store_item = [&](const u32x4_t (&buf)[NHI], int k, int h) {
+    const int it = tid + k * NT_;
+    // every item but the last is inside the halo for every thread
+    if ((k + 1) * NT_ <= HITEMS || it < HITEMS) {
+      const int p = it >> 3, q = it & 7;
+      const u32x4_t val = buf[k];
+      const unsigned h01 = pk_bf16(u2f(val[0]), u2f(val[1]));
+      const unsigned h23 = pk_bf16(u2f(val[2]), u2f(val[3]));
+      const unsigned l01 = pk_bf16(u2f(val[0]) - u2f(h01 << 16), u2f(val[1]) - u2f(h01 & 0xffff0000u));
+      const unsigned l23 = pk_bf16(u2f(val[2]) - u2f(h23 << 16), u2f(val[3]) - u2f(h23 & 0xffff0000u));
+      char* d = lin + p * C::PIXB + h * 64 + q * 8;
+      *reinterpret_cast<uint2*>(d) = uint2{h01, h23};
+      *reinterpret_cast<uint2*>(d + C::LO_OFF) = uint2{l01, l23};
+    }
+  };
+
+  u32x4_t b0[NHI], b1[NHI];
+  load_half(b0, t, 0, 0, NHI);
+  load_half(b1, t, 1, 0, NHI);
+  {
+    // this workgroup's hi and lo weight fragments into LDS, in fragment order
+    constexpr int NW = C::NCH * NJW * 64;
+    constexpr int NT = 2 * NW;
+    constexpr int PER = (NT + NT_ - 1) / NT_;
+    constexpr int WB = PER < 24 ? PER : 24;
+    u32x4_t* dst = reinterpret_cast<u32x4_t*>(smem + C::LDS_IN);
+    auto src = [&](int i) {
+      const int part = i >= NW ? 1 : 0, f = i - part * NW;
+      const int ln = f % 64, jj = (f / 64) % NJW, ch = f / (64 * NJW);
+      return (part * C::NCH * C::NJ + ch * C::NJ + jh * NJW + jj) * 64 + ln;
+    };
+    for (int q0 = 0; q0 < PER; q0 += WB) {
+      u32x4_t wbuf[WB];
+#pragma unroll
+      for (int q = 0; q < WB; ++q) {
+        const int i = tid + (q0 + q) * NT_;
+        if (i < NT) wbuf[q] = gw[src(i)];
+      }
+#pragma unroll
+      for (int q = 0; q < WB; ++q) {
+        const int i = tid + (q0 + q) * NT_;
+        if (i < NT) dst[i] = wbuf[q];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NHI; ++k) store_item(b0, k, 0);
+
+  float bias_r[NJW][4];
+  {
+    const float* bias = static_cast<const float*>(a.bias);
+#pragma unroll
+    for (int jj = 0; jj < NJW; ++jj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = 16 * (jh * NJW + jj) + 4 * g + i;
+        bias_r[jj][i] = (bias && co < CO) ? bias[co] : 0.f;
+      }
+  }
+
+  // the previous tile: accumulators, epilogue operand, position and the
+  // output resource over its rows (zero bytes before the first tile: every
+  // store dropped)
+  f32x4_t accp[RW][NJW];
+  u32x4_t e0v[RW][NJW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int j = 0; j < NJW; ++j) {
+      accp[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      e0v[r][j] = u32x4_t{0u, 0u, 0u, 0u};
+    }
+  int pty0 = 0, ptx0 = 0;
+  __amdgpu_buffer_rsrc_t prs = out_rsrc(a.out0, 0u);
+  auto piece = [&](int r, int jj) {
+    const int ly = wv * RW + r, oy = pty0 + ly, ox = ptx0 + c16;
+    const int co0 = 16 * (jh * NJW + jj) + 4 * g;
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float x = accp[r][jj][i];
+      // both forms computed and selected (no branch among the MFMAs)
+      if constexpr (EPI == E_ACT) {
+        const float hv = x + bias_r[jj][i];
+        const float y = softplus_hw(hv);
+        v[i] = sp ? y : hv;
+      } else if constexpr (EPI == E_DELTA) {
+        const float d = dsp_from_a_hw(u2f(e0v[r][jj][i]));
+        v[i] = (sp ? d : 1.f) * x;
+      } else {
+        v[i] = x;
+      }
+    }
+    const bool ok = oy < a.H && ox < a.W;
+    const unsigned off = ok ? (static_cast<unsigned>(ly * a.W + ox) * CO + co0) * 4u : kDropOffset;
+    const u32x4_v pk = {f2u(v[0]), f2u(v[1]), f2u(v[2]), f2u(v[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(pk, prs, static_cast<int>(off), 0, 0);
+  };
+
+  __syncthreads();  // the first tile's half 0 is in LDS
+
+  while (t < ntiles) {
+    const int tn = next_open(t);
+    const int ni = t / tiles_per_img;
+    const int rem = t - ni * tiles_per_img;
+    const int ty0 = (rem / ntx) * TH, tx0 = (rem % ntx) * TW;
+    if (a.work_px && tid == 0 && jh == 0) {
+      const int vh = a.H - ty0 < TH ? a.H - ty0 : TH, vw = a.W - tx0 < TW ? a.W - tx0 : TW;
+      atomicAdd(a.work_px, static_cast<unsigned long long>(vh * vw));
+    }
+    f32x4_t acc[RW][NJW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int j = 0; j < NJW; ++j) acc[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    // one channel half of the K loop: 3 (dx) x 3 (dy) groups of 3 RW NJW MFMAs,
+    // and after each group's MFMAs the side work `side(group)`
+    auto half = [&](const int c, auto&& side) {
+      u32x4_t rh[2][NR], rl[2][NR], afc[NJW], alc[NJW], afn[NJW], aln[NJW];
+      auto load_row = [&](int bsel, int ir, int dx) {
+        const int pix = (wv * RW + ir) * HW_ + c16 + dx;
+        const char* b = lin + pix * C::PIXB + c * 64 + g * 16;
+        rh[bsel][ir] = *reinterpret_cast<const u32x4_t*>(b);
+        rl[bsel][ir] = *reinterpret_cast<const u32x4_t*>(b + C::LO_OFF);
+      };
+      auto load_w = [&](u32x4_t* hi, u32x4_t* lo, int dx, int dy) {
+        const int ch = (dy * 3 + dx) * C::CPT + c;
+#pragma unroll
+        for (int j = 0; j < NJW; ++j) {
+          hi[j] = lw[(ch * NJW + j) * 64 + lane];
+          lo[j] = lwl[(ch * NJW + j) * 64 + lane];
+        }
+      };
+#pragma unroll
+      for (int ir = 0; ir < NR; ++ir) load_row(0, ir, 0);
+      load_w(afc, alc, 0, 0);
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int bs = dx & 1;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          // reads for later groups: a third of the next step's rows, the next
+          // group's weight fragments
+          if (dx < 2) {
+#pragma unroll
+            for (int ir = dy * NR / 3; ir < (dy + 1) * NR / 3; ++ir) load_row(bs ^ 1, ir, dx + 1);
+          }
+          if (dy < 2)
+            load_w(afn, aln, dx, dy + 1);
+          else if (dx < 2)
+            load_w(afn, aln, dx + 1, 0);
+#pragma unroll
+          for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rl[bs][r + dy]);
+#pragma unroll
+          for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], alc[j], rh[bs][r + dy]);
+#pragma unroll
+          for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rh[bs][r + dy]);
+          side(dx * 3 + dy);
+          // one wave per SIMD: spread this group's LDS reads, side work and
+          // memory operations between its MFMAs, so that they issue while the
+          // matrix core is busy
+#pragma unroll
+          for (int i = 0; i < 3 * RW * NJW; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            if (i < 8) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+            __builtin_amdgcn_sched_group_barrier(0x040, 1, 0);  // VMEM write
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int j = 0; j < NJW; ++j) {
+            afc[j] = afn[j];
+            alc[j] = aln[j];
+          }
+        }
+      }
+    };
+
+    // Side work, spread over the groups of the two halves.  Half 0: this
+    // tile's half 1 (b1) into LDS, items k and k + 9 in group k; from group 1
+    // (after group 0's wait for b1) b0 takes the next tile's half 0, a third of
+    // its loads per group; the previous tile's epilogue, two pieces per group
+    // in groups 1..4.  Half 1: the next tile's half 0 (b0) into LDS (past the
+    // last tile b0 holds zeros, stored to no effect), b1 takes the next tile's
+    // half 1, and this tile's sigma(h) operand is read.  Loads sit early in a
+    // half, the stores of the epilogue a half before the next wait.
+    constexpr int LA = (NHI + 2) / 3;
+    auto items = [&](const u32x4_t (&buf)[NHI], int grp, int h) {
+      store_item(buf, grp, h);
+      if (grp + 9 < NHI) store_item(buf, grp + 9, h);
+    };
+    half(0, [&](int grp) {
+      items(b1, grp, 1);
+      if (grp >= 1 && grp <= 3)
+        load_half(b0, tn, 0, (grp - 1) * LA, grp * LA < NHI ? grp * LA : NHI);
+      if (grp >= 1 && 2 * grp - 2 < RW * NJW) {
+        piece((2 * grp - 2) / NJW, (2 * grp - 2) % NJW);
+        piece((2 * grp - 1) / NJW, (2 * grp - 1) % NJW);
+      }
+    });
+    __syncthreads();  // half 1 is in LDS, half 0 has been read
+    half(1, [&](int grp) {
+      items(b0, grp, 0);
+      if (grp >= 1 && grp <= 3)
+        load_half(b1, tn, 1, (grp - 1) * LA, grp * LA < NHI ? grp * LA : NHI);
+      if (EPI == E_DELTA && (grp == 1 || grp == 2)) {
+        // this tile's sigma(h) (half of it per group), through a resource over
+        // its rows: pixels past the image edge read zero
+        const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
+        const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
+        const __amdgpu_buffer_rsrc_t ers =
+            out_rsrc(const_cast<char*>(static_cast<const char*>(a.e0)) + row0 * 4,
+                     static_cast<unsigned>(rows) * a.W * CO * 4);
+#pragma unroll
+        for (int r = (grp - 1) * RW / 2; r < grp * RW / 2; ++r)
+#pragma unroll
+          for (int jj = 0; jj < NJW; ++jj) {
+            const int ly = wv * RW + r, ox = tx0 + c16;
+            const int co0 = 16 * (jh * NJW + jj) + 4 * g;
+            const unsigned off = ox < a.W ? (static_cast<unsigned>(ly * a.W + ox) * CO + co0) * 4u
+                                          : kDropOffset;
+            const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(ers, static_cast<int>(off), 0, 0);
+            e0v[r][jj] = u32x4_t{v[0], v[1], v[2], v[3]};
+          }
+      }
+    });
+    __syncthreads();  // the next tile's half 0 is in LDS, half 1 has been read
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int j = 0; j < NJW; ++j) accp[r][j] = acc[r][j];
+    pty0 = ty0;
+    ptx0 = tx0;
+    {
+      const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
+      const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
+      prs = out_rsrc(static_cast<char*>(a.out0) + row0 * 4, static_cast<unsigned>(rows) * a.W * CO * 4);
+    }
+    t = tn;
+  }
+  // the last tile's epilogue
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int j = 0; j < NJW; ++j) piece(r, j);
+}
+
+// the halo loads address one image through 32-bit byte offsets
+inline bool split64_fits(const ConvArgs& a) {
+  return static_cast<long long>(a.H) * a.W * 256 < static_cast<long long>(kDropOffset);
+}
+
+template <int CO, int EPI>
+int launch_split64(const ConvArgs& a, hipStream_t s) {
+  using C = Cfg<PREC_SPLIT, 64, CO, P_NONE>;
+  static_assert(C::LDS <= 160 * 1024, "LDS budget");
+  static bool attr_set = false;
+  static int max_blocks = 0;
+  auto kern = conv_split64_kernel<CO, EPI>;
+  constexpr int THREADS = kS64Threads;
+  if (!attr_set) {
+    IDQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS));
+    int dev = 0, ncu = 0, occ = 0;
+    IDQ_HIP(hipGetDevice(&dev));
+    IDQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    IDQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, THREADS, C::LDS));
+    if (occ < 1) return fail(IDQ_E_UNSUPPORTED, "split conv does not fit on a compute unit");
+    max_blocks = ncu * occ;
+    attr_set = true;
+  }
+  const int ntx = (a.W + TW - 1) / TW, nty = (a.H + TH - 1) / TH;
+  if (static_cast<long long>(TH) * a.W * CO * 4 >= static_cast<long long>(kDropOffset))
+    return fail(IDQ_E_UNSUPPORTED, "image too wide for the MFMA conv");
+  const long long nt = static_cast<long long>(a.NI) * ntx * nty;
+  if (nt > 0x7fffffff) return fail(IDQ_E_INVAL, "too many tiles");
+  const int ntiles = static_cast<int>(nt);
+  const int walkers_max = max_blocks / C::CSPLIT > 0 ? max_blocks / C::CSPLIT : 1;
+  const int grid = (ntiles < walkers_max ? ntiles : walkers_max) * C::CSPLIT;
+  if (a.ev0) {
+    ConvArgs ac = a;
+    int nx = ntx, ny = nty, ntl = ntiles;
+    void* args[] = {&ac, &nx, &ny, &ntl};
+    IDQ_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(THREADS),
+                               args, C::LDS, s, a.ev0, a.ev1, 0));
+  } else {
+    kern<<<grid, THREADS, C::LDS, s>>>(a, ntx, nty, ntiles);
+  }
+  IDQ_HIP(hipGetLastError());
+  return IDQ_OK;
+}
+
+}  // namespace mfma
+}  // namespace idq
