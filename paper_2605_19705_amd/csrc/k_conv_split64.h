@@ -91,13 +91,30 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     return tt;
   };
 
-  // item k of a half: pixel it / 8 of the halo, channels 32 h + 4 (it % 8) ..
-  // + 3, it = tid + 256 k.  Read through a buffer resource over the tile's
-  // image: 32-bit offsets, and an offset outside it (a halo pixel beyond the
-  // image) reads zero
+  // Items of a half (16 bytes: 4 channels of one halo pixel).  Items 0..8 of
+  // a thread walk the 16 inner columns two rows at a time: row 2k + tid / 128,
+  // column 1 + (tid / 8) % 16, channel quad tid % 8, so that one item's offset
+  // is the thread's offset plus a uniform step.  Items 9 and 10 cover the two
+  // edge columns (288 items: e = tid + 256 (k - 9), row e / 16, column 0 or 17
+  // by bit 3 of e, quad e % 8).  Loads go through a buffer resource over the
+  // tile's image: 32-bit offsets, and an offset outside the image (a halo row
+  // above or below it, or an offset pushed past it for a column outside it)
+  // reads zero.  Branch-free, so that it can be scheduled among the MFMAs:
+  // past the last tile the resource covers zero bytes.
+  static_assert(NT_ == 256 && TW == 16 && NHI == 11, "halo item layout");
   const unsigned img_bytes = static_cast<unsigned>(a.H * a.W) * 256u;
-  // (branch-free, so that it can be scheduled among the MFMAs: past the last
-  // tile the resource covers zero bytes and every load reads zero)
+  const int col_i = 1 + ((tid >> 3) & 15), q_i = tid & 7, r0 = tid >> 7;
+  const int thr_int = (r0 * a.W + col_i) * 256 + q_i * 16;
+  const int lds_int = ((r0 * HW_ + col_i) * C::PIXB) + q_i * 8;
+  int e_row[2], e_col[2], thr_e[2], lds_e[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int e = tid + 256 * m;
+    e_row[m] = e >> 4;
+    e_col[m] = ((e >> 3) & 1) ? HW_ - 1 : 0;
+    thr_e[m] = (e_row[m] * a.W + e_col[m]) * 256 + (e & 7) * 16;
+    lds_e[m] = (e_row[m] * HW_ + e_col[m]) * C::PIXB + (e & 7) * 8;
+  }
   auto load_half = [&](u32x4_t (&buf)[NHI], int tt, int h, int k0, int k1) {
     const bool real = tt < ntiles;
     const int tc = real ? tt : 0;
@@ -106,32 +123,34 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     const __amdgpu_buffer_rsrc_t rs = out_rsrc(
         const_cast<char*>(static_cast<const char*>(a.in0)) + static_cast<size_t>(ni) * img_bytes,
         real ? img_bytes : 0u);
+    // byte offset of halo pixel (0, 0) of this tile and half (negative on the
+    // top row of images: those rows read zero)
+    const int org = ((ty0 - 1) * a.W + tx0 - 1) * 256 + h * 128;
+    const int base_i = tx0 - 1 + col_i < a.W ? thr_int : static_cast<int>(kDropOffset);
 #pragma unroll
     for (int k = k0; k < k1; ++k) {
-      const int it = tid + k * NT_;
-      const int p = it >> 3, q = it & 7;
-      const int ly = p / HW_, lx = p - (p / HW_) * HW_;
-      const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
-      const bool in = it < HITEMS && static_cast<unsigned>(gy) < static_cast<unsigned>(a.H) &&
-                      static_cast<unsigned>(gx) < static_cast<unsigned>(a.W);
-      const unsigned off = in ? static_cast<unsigned>((gy * a.W + gx) * 256 + h * 128 + q * 16)
-                              : kDropOffset;
-      const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(rs, static_cast<int>(off), 0, 0);
+      int off;
+      if (k < 9) {
+        off = base_i + (org + k * 2 * a.W * 256);
+      } else {
+        const int m = k - 9;
+        const bool ok = e_col[m] == 0 ? tx0 > 0 : tx0 + HW_ - 2 < a.W;
+        off = ok && tid + 256 * m < HITEMS ? thr_e[m] + org : static_cast<int>(kDropOffset);
+      }
+      const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
       buf[k] = u32x4_t{v[0], v[1], v[2], v[3]};
     }
   };
   // hi parts and bf16-rounded remainders of item k into the half's LDS bytes
   auto store_item = [&](const u32x4_t (&buf)[NHI], int k, int h) {
-    const int it = tid + k * NT_;
-    // every item but the last is inside the halo for every thread
-    if ((k + 1) * NT_ <= HITEMS || it < HITEMS) {
-      const int p = it >> 3, q = it & 7;
+    // items 0..9 exist for every thread, item 10 for the first 32
+    if (k < 10 || tid < HITEMS - 10 * NT_) {
       const u32x4_t val = buf[k];
       const unsigned h01 = pk_bf16(u2f(val[0]), u2f(val[1]));
       const unsigned h23 = pk_bf16(u2f(val[2]), u2f(val[3]));
       const unsigned l01 = pk_bf16(u2f(val[0]) - u2f(h01 << 16), u2f(val[1]) - u2f(h01 & 0xffff0000u));
       const unsigned l23 = pk_bf16(u2f(val[2]) - u2f(h23 << 16), u2f(val[3]) - u2f(h23 & 0xffff0000u));
-      char* d = lin + p * C::PIXB + h * 64 + q * 8;
+      char* d = lin + h * 64 + (k < 9 ? lds_int + k * 2 * HW_ * C::PIXB : lds_e[k < 9 ? 0 : k - 9]);
       *reinterpret_cast<uint2*>(d) = uint2{h01, h23};
       *reinterpret_cast<uint2*>(d + C::LO_OFF) = uint2{l01, l23};
     }
@@ -193,11 +212,13 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
       accp[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
       e0v[r][j] = u32x4_t{0u, 0u, 0u, 0u};
     }
-  int pty0 = 0, ptx0 = 0;
   __amdgpu_buffer_rsrc_t prs = out_rsrc(a.out0, 0u);
+  const int wvu = __builtin_amdgcn_readfirstlane(wv);
+  // lane part of a piece's byte offset in the previous tile's rows (past the
+  // image's right edge: pushed beyond the resource)
+  int plane = static_cast<int>(kDropOffset);
   auto piece = [&](int r, int jj) {
-    const int ly = wv * RW + r, oy = pty0 + ly, ox = ptx0 + c16;
-    const int co0 = 16 * (jh * NJW + jj) + 4 * g;
+    const int ly = wvu * RW + r;
     float v[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -214,10 +235,10 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
         v[i] = x;
       }
     }
-    const bool ok = oy < a.H && ox < a.W;
-    const unsigned off = ok ? (static_cast<unsigned>(ly * a.W + ox) * CO + co0) * 4u : kDropOffset;
+    // rows past the image's bottom edge fall outside the resource
+    const int off = plane + (ly * a.W * CO * 4 + jj * 64);
     const u32x4_v pk = {f2u(v[0]), f2u(v[1]), f2u(v[2]), f2u(v[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(pk, prs, static_cast<int>(off), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(pk, prs, off, 0, 0);
   };
 
   __syncthreads();  // the first tile's half 0 is in LDS
@@ -343,15 +364,14 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
         const __amdgpu_buffer_rsrc_t ers =
             out_rsrc(const_cast<char*>(static_cast<const char*>(a.e0)) + row0 * 4,
                      static_cast<unsigned>(rows) * a.W * CO * 4);
+        const int lane_off = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * 4
+                                             : static_cast<int>(kDropOffset);
 #pragma unroll
         for (int r = (grp - 1) * RW / 2; r < grp * RW / 2; ++r)
 #pragma unroll
           for (int jj = 0; jj < NJW; ++jj) {
-            const int ly = wv * RW + r, ox = tx0 + c16;
-            const int co0 = 16 * (jh * NJW + jj) + 4 * g;
-            const unsigned off = ox < a.W ? (static_cast<unsigned>(ly * a.W + ox) * CO + co0) * 4u
-                                          : kDropOffset;
-            const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(ers, static_cast<int>(off), 0, 0);
+            const int off = lane_off + ((wvu * RW + r) * a.W * CO * 4 + jj * 64);
+            const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(ers, off, 0, 0);
             e0v[r][jj] = u32x4_t{v[0], v[1], v[2], v[3]};
           }
       }
@@ -361,8 +381,8 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     for (int r = 0; r < RW; ++r)
 #pragma unroll
       for (int j = 0; j < NJW; ++j) accp[r][j] = acc[r][j];
-    pty0 = ty0;
-    ptx0 = tx0;
+    plane = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * 4
+                            : static_cast<int>(kDropOffset);
     {
       const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
       const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
@@ -379,7 +399,9 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
 
 // the halo loads address one image through 32-bit byte offsets
 inline bool split64_fits(const ConvArgs& a) {
-  return static_cast<long long>(a.H) * a.W * 256 < static_cast<long long>(kDropOffset);
+  // an offset pushed out of range (kDropOffset plus at most one image) must
+  // stay above the image and below 2^32, one pushed below zero stay negative
+  return static_cast<long long>(a.H) * a.W * 256 <= (1LL << 30) && a.W >= 16;
 }
 
 template <int CO, int EPI>
