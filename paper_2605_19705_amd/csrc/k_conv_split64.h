@@ -1,5 +1,6 @@
 // Split-bf16 3x3 convolution from 64 input channels (to 32 or 64 outputs),
-// software-pipelined over the two halves of the input channels.
+// software-pipelined over the two halves of the input channels, with the
+// halo traffic on waves of its own.
 //
 // Same arithmetic as the split form of conv_mfma_kernel (k_conv_mfma.h): float
 // activations and float weights each taken as a bf16 hi part plus the bf16
@@ -7,31 +8,26 @@
 // v_mfma_f32_16x16x32_bf16, 32 output channels per workgroup (two workgroups
 // per tile for 64 outputs, on one XCD), the 18 x 18 halo tile and this
 // workgroup's hi and lo weight fragments in LDS (161,856 bytes: one workgroup
-// per compute unit).  4 waves of 4 output rows: one wave per SIMD with the
-// whole register file (the pipeline below holds two accumulator sets, two
-// halo halves and double-buffered fragments), its matrix-core groups of 24
-// MFMAs long enough to cover one group's LDS reads.
+// per compute unit).
 //
 // What differs is the schedule.  The K loop runs channel half 0 (K chunks of
 // input channels 0..31, all 9 taps) and then channel half 1.  Each half reads
-// only its own bytes of every halo pixel, so while the waves run half 0 of
-// tile t, half 1 of the same tile goes from registers into LDS, and while they
-// run half 1, half 0 of the next tile does: the LDS stage overlaps the
-// matrix-core work instead of sitting between tiles, and the LDS footprint
-// stays that of one tile.  The epilogue (SoftPlus or sigma', stores) of tile t
-// is issued in pieces during half 0 of tile t + 1, the halo loads from HBM one
-// half ahead of their LDS stage.  Per wave and (dx, chunk) step the six input
-// rows are read once for the three kernel rows (dy) that use them, a third of
-// them per group during the previous step; weight fragment reads are issued
-// one matrix-core group ahead; MFMAs, LDS and memory operations are
-// interleaved by scheduling-group hints.
-//
-// Waits on the vector memory counter: it retires loads and stores in one
-// count, and a wait for a load while stores are outstanding waits for those
-// stores as well.  So each half first consumes the halo registers loaded a
-// half earlier (one wait, for memory issued at least a half before) and only
-// then issues the next loads; the epilogue's stores sit early in half 0, most
-// of a half before the next such wait.
+// only its own bytes of every halo pixel, so while half 0 of tile t is on the
+// matrix cores, half 1 of the same tile goes from registers into LDS, and
+// while half 1 is, half 0 of the next tile does: the LDS footprint stays that
+// of one tile.  The workgroup's 8 waves split the work: waves 0..3 (one per
+// SIMD, 4 output rows each) run the K loop and the epilogue; waves 4..7 load
+// the halo from HBM one half ahead, split it into hi and lo parts and write it
+// to LDS.  A vector memory instruction in a wave that feeds the matrix core
+// holds up its MFMA stream; on the helper waves it only occupies the SIMD's
+// issue slots the MFMA wave leaves free.  The epilogue (SoftPlus or sigma',
+// stores) of a tile follows its K loop.  Per matrix wave and (dx, chunk)
+// step the six input rows are read once for the three kernel rows (dy) that
+// use them, a third of them per group during the previous step; weight
+// fragment reads are issued one matrix-core group ahead; scheduling-group
+// hints spread the reads between the MFMAs.  Both kinds of wave walk the same
+// tiles and meet at the same two barriers per tile, in loops of their own (so
+// that their registers are not live at once).
 #pragma once
 
 #include "k_conv_mfma.h"
@@ -39,7 +35,7 @@
 namespace idq {
 namespace mfma {
 
-constexpr int kS64Threads = 256;
+constexpr int kS64Threads = 512;  // 4 matrix waves, then 4 halo waves
 
 template <int CO, int EPI>
 __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a, int ntx,
@@ -48,11 +44,11 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
   static_assert(C::NJW == 2 && C::CPT == 2 && C::WLO_LDS && C::LO_OFF == 128 && C::KC == 32,
                 "shape of the channel-half pipeline");
   static_assert(EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW, "NHWC float outputs");
-  constexpr int NT_ = kS64Threads, RW = TH / (NT_ / 64), NJW = 2, NR = RW + 2;
+  constexpr int NT_ = kS64Threads / 2, RW = TH / (NT_ / 64), NJW = 2, NR = RW + 2;
+
   // 16-byte items (4 channels of one pixel) of one channel half, per thread
   constexpr int HITEMS = NPIX * 8;
   constexpr int NHI = (HITEMS + NT_ - 1) / NT_;
-  static_assert(NHI > 9 && NHI <= 2 * 9, "items of a half are staged one or two per group");
   static_assert(RW * NJW % 2 == 0 && RW * NJW / 2 + 1 < 9 && RW % 2 == 0,
                 "epilogue pieces fit half 0");
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -103,13 +99,14 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
   // past the last tile the resource covers zero bytes.
   static_assert(NT_ == 256 && TW == 16 && NHI == 11, "halo item layout");
   const unsigned img_bytes = static_cast<unsigned>(a.H * a.W) * 256u;
-  const int col_i = 1 + ((tid >> 3) & 15), q_i = tid & 7, r0 = tid >> 7;
+  const int htid = tid & (NT_ - 1);  // thread index among the halo waves
+  const int col_i = 1 + ((htid >> 3) & 15), q_i = htid & 7, r0 = htid >> 7;
   const int thr_int = (r0 * a.W + col_i) * 256 + q_i * 16;
   const int lds_int = ((r0 * HW_ + col_i) * C::PIXB) + q_i * 8;
   int e_row[2], e_col[2], thr_e[2], lds_e[2];
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    const int e = tid + 256 * m;
+    const int e = htid + 256 * m;
     e_row[m] = e >> 4;
     e_col[m] = ((e >> 3) & 1) ? HW_ - 1 : 0;
     thr_e[m] = (e_row[m] * a.W + e_col[m]) * 256 + (e & 7) * 16;
@@ -135,7 +132,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
       } else {
         const int m = k - 9;
         const bool ok = e_col[m] == 0 ? tx0 > 0 : tx0 + HW_ - 2 < a.W;
-        off = ok && tid + 256 * m < HITEMS ? thr_e[m] + org : static_cast<int>(kDropOffset);
+        off = ok && htid + 256 * m < HITEMS ? thr_e[m] + org : static_cast<int>(kDropOffset);
       }
       const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
       buf[k] = u32x4_t{v[0], v[1], v[2], v[3]};
@@ -144,7 +141,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
   // hi parts and bf16-rounded remainders of item k into the half's LDS bytes
   auto store_item = [&](const u32x4_t (&buf)[NHI], int k, int h) {
     // items 0..9 exist for every thread, item 10 for the first 32
-    if (k < 10 || tid < HITEMS - 10 * NT_) {
+    if (k < 10 || htid < HITEMS - 10 * NT_) {
       const u32x4_t val = buf[k];
       const unsigned h01 = pk_bf16(u2f(val[0]), u2f(val[1]));
       const unsigned h23 = pk_bf16(u2f(val[2]), u2f(val[3]));
@@ -156,14 +153,17 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     }
   };
 
+  const bool halo_wave = tid >= NT_;
   u32x4_t b0[NHI], b1[NHI];
-  load_half(b0, t, 0, 0, NHI);
-  load_half(b1, t, 1, 0, NHI);
+  if (halo_wave) {
+    load_half(b0, t, 0, 0, NHI);
+    load_half(b1, t, 1, 0, NHI);
+  }
   {
     // this workgroup's hi and lo weight fragments into LDS, in fragment order
     constexpr int NW = C::NCH * NJW * 64;
     constexpr int NT = 2 * NW;
-    constexpr int PER = (NT + NT_ - 1) / NT_;
+    constexpr int PER = (NT + kS64Threads - 1) / kS64Threads;
     constexpr int WB = PER < 24 ? PER : 24;
     u32x4_t* dst = reinterpret_cast<u32x4_t*>(smem + C::LDS_IN);
     auto src = [&](int i) {
@@ -175,57 +175,72 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
       u32x4_t wbuf[WB];
 #pragma unroll
       for (int q = 0; q < WB; ++q) {
-        const int i = tid + (q0 + q) * NT_;
+        const int i = tid + (q0 + q) * kS64Threads;
         if (i < NT) wbuf[q] = gw[src(i)];
       }
 #pragma unroll
       for (int q = 0; q < WB; ++q) {
-        const int i = tid + (q0 + q) * NT_;
+        const int i = tid + (q0 + q) * kS64Threads;
         if (i < NT) dst[i] = wbuf[q];
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < NHI; ++k) store_item(b0, k, 0);
-
-  float bias_r[NJW][4];
-  {
+  // this workgroup's 32 biases, after the weights (read by the epilogue)
+  float* lbias = reinterpret_cast<float*>(smem + C::LDS);
+  if (tid < 16 * NJW) {
     const float* bias = static_cast<const float*>(a.bias);
+    const int co = 16 * jh * NJW + tid;
+    lbias[tid] = (bias && co < CO) ? bias[co] : 0.f;
+  }
+  if (halo_wave) {
 #pragma unroll
-    for (int jj = 0; jj < NJW; ++jj)
+    for (int k = 0; k < NHI; ++k) store_item(b0, k, 0);
+  }
+  __syncthreads();  // the first tile's half 0, the weights and biases are in LDS
+
+  if (halo_wave) {
+    // Halo waves.  Half 0 of tile t: t's half 1 (b1) into LDS, then b0 takes
+    // the next tile's half 0.  Half 1: that into LDS (past the last tile b0
+    // holds zeros, stored to no effect), then b1 takes the next tile's half 1.
+    // Each half waits once, for loads issued a half earlier.
+    while (t < ntiles) {
+      const int tn = next_open(t);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int co = 16 * (jh * NJW + jj) + 4 * g + i;
-        bias_r[jj][i] = (bias && co < CO) ? bias[co] : 0.f;
-      }
+      for (int k = 0; k < NHI; ++k) store_item(b1, k, 1);
+      load_half(b0, tn, 0, 0, NHI);
+      __syncthreads();  // half 1 of t is in LDS; the matrix waves are done with half 0
+#pragma unroll
+      for (int k = 0; k < NHI; ++k) store_item(b0, k, 0);
+      load_half(b1, tn, 1, 0, NHI);
+      __syncthreads();  // half 0 of tn is in LDS; the matrix waves are done with half 1
+      t = tn;
+    }
+    return;
   }
 
-  // the previous tile: accumulators, epilogue operand, position and the
-  // output resource over its rows (zero bytes before the first tile: every
-  // store dropped)
-  f32x4_t accp[RW][NJW];
+  // the tile's sigma(h) operand (E_DELTA)
   u32x4_t e0v[RW][NJW];
 #pragma unroll
   for (int r = 0; r < RW; ++r)
 #pragma unroll
-    for (int j = 0; j < NJW; ++j) {
-      accp[r][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      e0v[r][j] = u32x4_t{0u, 0u, 0u, 0u};
-    }
+    for (int j = 0; j < NJW; ++j) e0v[r][j] = u32x4_t{0u, 0u, 0u, 0u};
+  // the output resource over the tile's rows, and the lane part of a piece's
+  // byte offset in them (past the image's right edge: pushed beyond the
+  // resource)
   __amdgpu_buffer_rsrc_t prs = out_rsrc(a.out0, 0u);
   const int wvu = __builtin_amdgcn_readfirstlane(wv);
-  // lane part of a piece's byte offset in the previous tile's rows (past the
-  // image's right edge: pushed beyond the resource)
   int plane = static_cast<int>(kDropOffset);
-  auto piece = [&](int r, int jj) {
+  auto piece = [&](int r, int jj, const f32x4_t& accv) {
     const int ly = wvu * RW + r;
     float v[4];
+    float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (EPI == E_ACT) bias4 = *reinterpret_cast<const float4*>(lbias + 16 * jj + 4 * g);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float x = accp[r][jj][i];
+      const float x = accv[i];
       // both forms computed and selected (no branch among the MFMAs)
       if constexpr (EPI == E_ACT) {
-        const float hv = x + bias_r[jj][i];
+        const float hv = x + (i == 0 ? bias4.x : i == 1 ? bias4.y : i == 2 ? bias4.z : bias4.w);
         const float y = softplus_hw(hv);
         v[i] = sp ? y : hv;
       } else if constexpr (EPI == E_DELTA) {
@@ -240,8 +255,6 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     const u32x4_v pk = {f2u(v[0]), f2u(v[1]), f2u(v[2]), f2u(v[3])};
     __builtin_amdgcn_raw_buffer_store_b128(pk, prs, off, 0, 0);
   };
-
-  __syncthreads();  // the first tile's half 0 is in LDS
 
   while (t < ntiles) {
     const int tn = next_open(t);
@@ -261,12 +274,16 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     // one channel half of the K loop: 3 (dx) x 3 (dy) groups of 3 RW NJW MFMAs,
     // and after each group's MFMAs the side work `side(group)`
     auto half = [&](const int c, auto&& side) {
-      u32x4_t rh[2][NR], rl[2][NR], afc[NJW], alc[NJW], afn[NJW], aln[NJW];
-      auto load_row = [&](int bsel, int ir, int dx) {
+      // eight row slots: step dx holds its input row ir in slot kSlot[dx][ir];
+      // a slot is refilled as soon as the kernel rows (dy) of its row are done
+      static_assert(RW == 4, "row slot table for 4 output rows per wave");
+      constexpr int kSlot[3][6] = {{0, 1, 2, 3, 4, 5}, {6, 7, 0, 1, 2, 3}, {4, 5, 6, 7, 0, 1}};
+      u32x4_t rh[8], rl[8], afc[NJW], alc[NJW], afn[NJW], aln[NJW];
+      auto load_row = [&](int dx, int ir) {
         const int pix = (wv * RW + ir) * HW_ + c16 + dx;
         const char* b = lin + pix * C::PIXB + c * 64 + g * 16;
-        rh[bsel][ir] = *reinterpret_cast<const u32x4_t*>(b);
-        rl[bsel][ir] = *reinterpret_cast<const u32x4_t*>(b + C::LO_OFF);
+        rh[kSlot[dx][ir]] = *reinterpret_cast<const u32x4_t*>(b);
+        rl[kSlot[dx][ir]] = *reinterpret_cast<const u32x4_t*>(b + C::LO_OFF);
       };
       auto load_w = [&](u32x4_t* hi, u32x4_t* lo, int dx, int dy) {
         const int ch = (dy * 3 + dx) * C::CPT + c;
@@ -277,18 +294,27 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
         }
       };
 #pragma unroll
-      for (int ir = 0; ir < NR; ++ir) load_row(0, ir, 0);
+      for (int ir = 0; ir < NR; ++ir) load_row(0, ir);
       load_w(afc, alc, 0, 0);
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        const int bs = dx & 1;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-          // reads for later groups: a third of the next step's rows, the next
+          // reads for later groups: rows into slots freed by earlier groups
+          // (this step's rows 4 and 5 and the next step's rows 0 and 1 in group
+          // 0, the next step's rows 2 and 3 in groups 1 and 2), the next
           // group's weight fragments
+          if (dy == 0 && dx > 0) {
+            load_row(dx, 4);
+            load_row(dx, 5);
+          }
           if (dx < 2) {
-#pragma unroll
-            for (int ir = dy * NR / 3; ir < (dy + 1) * NR / 3; ++ir) load_row(bs ^ 1, ir, dx + 1);
+            if (dy == 0) {
+              load_row(dx + 1, 0);
+              load_row(dx + 1, 1);
+            } else {
+              load_row(dx + 1, dy + 1);
+            }
           }
           if (dy < 2)
             load_w(afn, aln, dx, dy + 1);
@@ -297,19 +323,17 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
 #pragma unroll
           for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rl[bs][r + dy]);
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rl[kSlot[dx][r + dy]]);
 #pragma unroll
           for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], alc[j], rh[bs][r + dy]);
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], alc[j], rh[kSlot[dx][r + dy]]);
 #pragma unroll
           for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rh[bs][r + dy]);
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rh[kSlot[dx][r + dy]]);
           side(dx * 3 + dy);
-          // one wave per SIMD: spread this group's LDS reads, side work and
-          // memory operations between its MFMAs, so that they issue while the
-          // matrix core is busy
+          // spread this group's LDS reads and epilogue work between its MFMAs
 #pragma unroll
           for (int i = 0; i < 3 * RW * NJW; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
@@ -329,34 +353,15 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
       }
     };
 
-    // Side work, spread over the groups of the two halves.  Half 0: this
-    // tile's half 1 (b1) into LDS, items k and k + 9 in group k; from group 1
-    // (after group 0's wait for b1) b0 takes the next tile's half 0, a third of
-    // its loads per group; the previous tile's epilogue, two pieces per group
-    // in groups 1..4.  Half 1: the next tile's half 0 (b0) into LDS (past the
-    // last tile b0 holds zeros, stored to no effect), b1 takes the next tile's
-    // half 1, and this tile's sigma(h) operand is read.  Loads sit early in a
-    // half, the stores of the epilogue a half before the next wait.
-    constexpr int LA = (NHI + 2) / 3;
-    auto items = [&](const u32x4_t (&buf)[NHI], int grp, int h) {
-      store_item(buf, grp, h);
-      if (grp + 9 < NHI) store_item(buf, grp + 9, h);
-    };
-    half(0, [&](int grp) {
-      items(b1, grp, 1);
-      if (grp >= 1 && grp <= 3)
-        load_half(b0, tn, 0, (grp - 1) * LA, grp * LA < NHI ? grp * LA : NHI);
-      if (grp >= 1 && 2 * grp - 2 < RW * NJW) {
-        piece((2 * grp - 2) / NJW, (2 * grp - 2) % NJW);
-        piece((2 * grp - 1) / NJW, (2 * grp - 1) % NJW);
-      }
-    });
+    // Side work of the matrix waves: this tile's sigma(h) operand, read in
+    // groups 5..6 of half 1 (not held through the rest of it).  The epilogue
+    // follows the K loop: holding a second accumulator set to overlap it with
+    // the next tile's K loop takes more registers than two waves per SIMD have
+    // (and measured no faster where it fitted).
+    half(0, [&](int) {});
     __syncthreads();  // half 1 is in LDS, half 0 has been read
     half(1, [&](int grp) {
-      items(b0, grp, 0);
-      if (grp >= 1 && grp <= 3)
-        load_half(b1, tn, 1, (grp - 1) * LA, grp * LA < NHI ? grp * LA : NHI);
-      if (EPI == E_DELTA && (grp == 1 || grp == 2)) {
+      if (EPI == E_DELTA && (grp == 5 || grp == 6)) {
         // this tile's sigma(h) (half of it per group), through a resource over
         // its rows: pixels past the image edge read zero
         const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
         const int lane_off = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * 4
                                              : static_cast<int>(kDropOffset);
 #pragma unroll
-        for (int r = (grp - 1) * RW / 2; r < grp * RW / 2; ++r)
+        for (int r = (grp - 5) * RW / 2; r < (grp - 4) * RW / 2; ++r)
 #pragma unroll
           for (int jj = 0; jj < NJW; ++jj) {
             const int off = lane_off + ((wvu * RW + r) * a.W * CO * 4 + jj * 64);
@@ -377,10 +382,6 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
       }
     });
     __syncthreads();  // the next tile's half 0 is in LDS, half 1 has been read
-#pragma unroll
-    for (int r = 0; r < RW; ++r)
-#pragma unroll
-      for (int j = 0; j < NJW; ++j) accp[r][j] = acc[r][j];
     plane = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * 4
                             : static_cast<int>(kDropOffset);
     {
@@ -388,13 +389,12 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
       const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
       prs = out_rsrc(static_cast<char*>(a.out0) + row0 * 4, static_cast<unsigned>(rows) * a.W * CO * 4);
     }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int j = 0; j < NJW; ++j) piece(r, j, acc[r][j]);
     t = tn;
   }
-  // the last tile's epilogue
-#pragma unroll
-  for (int r = 0; r < RW; ++r)
-#pragma unroll
-    for (int j = 0; j < NJW; ++j) piece(r, j);
 }
 
 // the halo loads address one image through 32-bit byte offsets
@@ -407,18 +407,19 @@ inline bool split64_fits(const ConvArgs& a) {
 template <int CO, int EPI>
 int launch_split64(const ConvArgs& a, hipStream_t s) {
   using C = Cfg<PREC_SPLIT, 64, CO, P_NONE>;
-  static_assert(C::LDS <= 160 * 1024, "LDS budget");
+  constexpr int LDS = C::LDS + 16 * 2 * 4;  // + this workgroup's biases
+  static_assert(LDS <= 160 * 1024, "LDS budget");
   static bool attr_set = false;
   static int max_blocks = 0;
   auto kern = conv_split64_kernel<CO, EPI>;
   constexpr int THREADS = kS64Threads;
   if (!attr_set) {
     IDQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS));
     int dev = 0, ncu = 0, occ = 0;
     IDQ_HIP(hipGetDevice(&dev));
     IDQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    IDQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, THREADS, C::LDS));
+    IDQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, THREADS, LDS));
     if (occ < 1) return fail(IDQ_E_UNSUPPORTED, "split conv does not fit on a compute unit");
     max_blocks = ncu * occ;
     attr_set = true;
@@ -436,9 +437,9 @@ int launch_split64(const ConvArgs& a, hipStream_t s) {
     int nx = ntx, ny = nty, ntl = ntiles;
     void* args[] = {&ac, &nx, &ny, &ntl};
     IDQ_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(THREADS),
-                               args, C::LDS, s, a.ev0, a.ev1, 0));
+                               args, LDS, s, a.ev0, a.ev1, 0));
   } else {
-    kern<<<grid, THREADS, C::LDS, s>>>(a, ntx, nty, ntiles);
+    kern<<<grid, THREADS, LDS, s>>>(a, ntx, nty, ntiles);
   }
   IDQ_HIP(hipGetLastError());
   return IDQ_OK;
