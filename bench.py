@@ -48,12 +48,13 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
     "conv64_bf16": {"bytes_per_px": 336.90,
-                    "sha256": "92248610fb8ea9d2b7ba089b5f0e0e84a817e8ec4db9444850d4db30bac81022",
+                    "sha256": "50e5dc950ca482dd7740b759244d83aeccdc69f651b5e18f27c4df722d1bea14",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
-    "conv64_bf16x3": {"bytes_per_px": 672.85,
-                      "sha256": "4439c5b94092bdce30056056287084318d9fbfd1a6f585a954a4d86bd6a12a4e",
+    "conv64_bf16x3": {"bytes_per_px": 673.35,
+                      "sha256": "175c754aeec55a92e4083d33a99d01b9dae80154abe825815029b0d0f4a09140",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
+                                  "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},
 }
 
@@ -485,7 +486,8 @@ def main():
                             if sources_sha256(tr["sources"]) == tr["sha256"] else None),
                 "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": per_px * px / launches,
-                "kernel": "conv_mfma_kernel<%s, 64, 64>" % ("bf16x3" if split else "bf16"),
+                "kernel": ("conv_split64_kernel<64>" if split
+                           else "conv_mfma_kernel<bf16, 64, 64>"),
                 "launches": launches, "sampled_every": args.sample_every,
                 "matrix_core_products_per_flop": 3 if split else 1,
                 "frac_of_product_ceiling": achieved / (peak / (3.0 if split else 1.0)),
