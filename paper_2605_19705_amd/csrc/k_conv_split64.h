@@ -100,7 +100,12 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
   static_assert(NT_ == 256 && TW == 16 && NHI == 11, "halo item layout");
   const unsigned img_bytes = static_cast<unsigned>(a.H * a.W) * 256u;
   const int htid = tid & (NT_ - 1);  // thread index among the halo waves
-  const int col_i = 1 + ((htid >> 3) & 15), q_i = htid & 7, r0 = htid >> 7;
+  // inner column of this thread's items: 8-lane groups take columns in the
+  // order 0, 4, 1, 5, 2, 6, 3, 7, 8, 12, ..., so that the two groups of 16
+  // lanes an LDS write serves together hit different banks (4 pixels apart)
+  const int jcol = (htid >> 3) & 15;
+  const int col_i = 1 + ((jcol & 1) << 2) + ((jcol >> 1) & 3) + (jcol & 8), q_i = htid & 7,
+            r0 = htid >> 7;
   const int thr_int = (r0 * a.W + col_i) * 256 + q_i * 16;
   const int lds_int = ((r0 * HW_ + col_i) * C::PIXB) + q_i * 8;
   int e_row[2], e_col[2], thr_e[2], lds_e[2];
