@@ -12,11 +12,11 @@ template <int CI, int CO>
 int by_epi(const ConvArgs& a, hipStream_t s) {
   if constexpr (CI == 64) {
     // channel-half pipelined kernel (k_conv_split64.h)
-    if (split64_fits(a)) {
+    if (halves_fits(a)) {
       switch (a.epi) {
-        case E_ACT: return launch_split64<CO, E_ACT>(a, s);
-        case E_DELTA: return launch_split64<CO, E_DELTA>(a, s);
-        case E_RAW: return launch_split64<CO, E_RAW>(a, s);
+        case E_ACT: return launch_halves<PREC_SPLIT, CO, E_ACT>(a, s);
+        case E_DELTA: return launch_halves<PREC_SPLIT, CO, E_DELTA>(a, s);
+        case E_RAW: return launch_halves<PREC_SPLIT, CO, E_RAW>(a, s);
         default: return fail(IDQ_E_UNSUPPORTED, "no split-bf16 MFMA epilogue of this kind");
       }
     }

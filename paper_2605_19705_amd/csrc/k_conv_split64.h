@@ -1,14 +1,15 @@
-// Split-bf16 3x3 convolution from 64 input channels (to 32 or 64 outputs),
-// software-pipelined over the two halves of the input channels, with the
-// halo traffic on waves of its own.
+// Split-bf16 and float32 3x3 convolutions from 64 input channels (to 32 or 64
+// outputs), software-pipelined over the two halves of the input channels,
+// with the halo traffic on waves of its own.
 //
-// Same arithmetic as the split form of conv_mfma_kernel (k_conv_mfma.h): float
+// Same arithmetic as conv_mfma_kernel (k_conv_mfma.h).  Split: float
 // activations and float weights each taken as a bf16 hi part plus the bf16
 // rounding of the remainder, acc += W_lo x_hi + W_hi x_lo + W_hi x_hi on
-// v_mfma_f32_16x16x32_bf16, 32 output channels per workgroup (two workgroups
-// per tile for 64 outputs, on one XCD), the 18 x 18 halo tile and this
-// workgroup's hi and lo weight fragments in LDS (161,856 bytes: one workgroup
-// per compute unit).
+// v_mfma_f32_16x16x32_bf16.  Float32: v_mfma_f32_16x16x4f32 on float4 slices of
+// 16-channel K chunks.  32 output channels per workgroup (two workgroups per
+// tile for 64 outputs, on one XCD), the 18 x 18 halo tile and this workgroup's
+// weight fragments (split: hi and lo) in LDS (161,856 bytes: one workgroup per
+// compute unit).
 //
 // What differs is the schedule.  The K loop runs channel half 0 (K chunks of
 // input channels 0..31, all 9 taps) and then channel half 1.  Each half reads
@@ -37,20 +38,26 @@ namespace mfma {
 
 constexpr int kS64Threads = 512;  // 4 matrix waves, then 4 halo waves
 
-template <int CO, int EPI>
-__global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a, int ntx,
-                                                                      int nty, int ntiles) {
-  using C = Cfg<PREC_SPLIT, 64, CO, P_NONE>;
-  static_assert(C::NJW == 2 && C::CPT == 2 && C::WLO_LDS && C::LO_OFF == 128 && C::KC == 32,
+template <int PREC, int CO, int EPI>
+__global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a, int ntx,
+                                                                     int nty, int ntiles) {
+  using C = Cfg<PREC, 64, CO, P_NONE>;
+  constexpr bool SPLIT = PREC == PREC_SPLIT;
+  static_assert(SPLIT || PREC == PREC_F32, "split-bf16 or float32 arithmetic");
+  static_assert(C::NJW == 2 && TW == 16 && C::WLDS && (!SPLIT || C::WLO_LDS) &&
+                    (SPLIT ? (C::CPT == 2 && C::LO_OFF == 128) : C::CPT == 4),
                 "shape of the channel-half pipeline");
   static_assert(EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW, "NHWC float outputs");
   constexpr int NT_ = kS64Threads / 2, RW = TH / (NT_ / 64), NJW = 2, NR = RW + 2;
+  // K chunks of one half per tap (split: 32 channels; float32: 2 x 16), and
+  // the LDS bytes of a channel quad and of a half within a halo pixel
+  constexpr int CPH = C::CPT / 2;
+  constexpr int QB = SPLIT ? 8 : 16, HB = SPLIT ? 64 : 128;
 
   // 16-byte items (4 channels of one pixel) of one channel half, per thread
   constexpr int HITEMS = NPIX * 8;
   constexpr int NHI = (HITEMS + NT_ - 1) / NT_;
-  static_assert(RW * NJW % 2 == 0 && RW * NJW / 2 + 1 < 9 && RW % 2 == 0,
-                "epilogue pieces fit half 0");
+  static_assert(RW % 2 == 0, "sigma(h) is read in two groups");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   char* lin = smem;
   const u32x4_t* lw = reinterpret_cast<const u32x4_t*>(smem + C::LDS_IN);
@@ -107,7 +114,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
   const int col_i = 1 + ((jcol & 1) << 2) + ((jcol >> 1) & 3) + (jcol & 8), q_i = htid & 7,
             r0 = htid >> 7;
   const int thr_int = (r0 * a.W + col_i) * 256 + q_i * 16;
-  const int lds_int = ((r0 * HW_ + col_i) * C::PIXB) + q_i * 8;
+  const int lds_int = ((r0 * HW_ + col_i) * C::PIXB) + q_i * QB;
   int e_row[2], e_col[2], thr_e[2], lds_e[2];
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
@@ -115,7 +122,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     e_row[m] = e >> 4;
     e_col[m] = ((e >> 3) & 1) ? HW_ - 1 : 0;
     thr_e[m] = (e_row[m] * a.W + e_col[m]) * 256 + (e & 7) * 16;
-    lds_e[m] = (e_row[m] * HW_ + e_col[m]) * C::PIXB + (e & 7) * 8;
+    lds_e[m] = (e_row[m] * HW_ + e_col[m]) * C::PIXB + (e & 7) * QB;
   }
   auto load_half = [&](u32x4_t (&buf)[NHI], int tt, int h, int k0, int k1) {
     const bool real = tt < ntiles;
@@ -143,18 +150,23 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
       buf[k] = u32x4_t{v[0], v[1], v[2], v[3]};
     }
   };
-  // hi parts and bf16-rounded remainders of item k into the half's LDS bytes
+  // item k into the half's LDS bytes: split, the hi parts and the
+  // bf16-rounded remainders; float32, the values
   auto store_item = [&](const u32x4_t (&buf)[NHI], int k, int h) {
     // items 0..9 exist for every thread, item 10 for the first 32
     if (k < 10 || htid < HITEMS - 10 * NT_) {
       const u32x4_t val = buf[k];
-      const unsigned h01 = pk_bf16(u2f(val[0]), u2f(val[1]));
-      const unsigned h23 = pk_bf16(u2f(val[2]), u2f(val[3]));
-      const unsigned l01 = pk_bf16(u2f(val[0]) - u2f(h01 << 16), u2f(val[1]) - u2f(h01 & 0xffff0000u));
-      const unsigned l23 = pk_bf16(u2f(val[2]) - u2f(h23 << 16), u2f(val[3]) - u2f(h23 & 0xffff0000u));
-      char* d = lin + h * 64 + (k < 9 ? lds_int + k * 2 * HW_ * C::PIXB : lds_e[k < 9 ? 0 : k - 9]);
-      *reinterpret_cast<uint2*>(d) = uint2{h01, h23};
-      *reinterpret_cast<uint2*>(d + C::LO_OFF) = uint2{l01, l23};
+      char* d = lin + h * HB + (k < 9 ? lds_int + k * 2 * HW_ * C::PIXB : lds_e[k < 9 ? 0 : k - 9]);
+      if constexpr (SPLIT) {
+        const unsigned h01 = pk_bf16(u2f(val[0]), u2f(val[1]));
+        const unsigned h23 = pk_bf16(u2f(val[2]), u2f(val[3]));
+        const unsigned l01 = pk_bf16(u2f(val[0]) - u2f(h01 << 16), u2f(val[1]) - u2f(h01 & 0xffff0000u));
+        const unsigned l23 = pk_bf16(u2f(val[2]) - u2f(h23 << 16), u2f(val[3]) - u2f(h23 & 0xffff0000u));
+        *reinterpret_cast<uint2*>(d) = uint2{h01, h23};
+        *reinterpret_cast<uint2*>(d + C::LO_OFF) = uint2{l01, l23};
+      } else {
+        *reinterpret_cast<u32x4_t*>(d) = val;
+      }
     }
   };
 
@@ -167,7 +179,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
   {
     // this workgroup's hi and lo weight fragments into LDS, in fragment order
     constexpr int NW = C::NCH * NJW * 64;
-    constexpr int NT = 2 * NW;
+    constexpr int NT = (SPLIT ? 2 : 1) * NW;  // hi and lo fragments for split
     constexpr int PER = (NT + kS64Threads - 1) / kS64Threads;
     constexpr int WB = PER < 24 ? PER : 24;
     u32x4_t* dst = reinterpret_cast<u32x4_t*>(smem + C::LDS_IN);
@@ -279,68 +291,80 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
     // one channel half of the K loop: 3 (dx) x 3 (dy) groups of 3 RW NJW MFMAs,
     // and after each group's MFMAs the side work `side(group)`
     auto half = [&](const int c, auto&& side) {
-      // eight row slots: step dx holds its input row ir in slot kSlot[dx][ir];
-      // a slot is refilled as soon as the kernel rows (dy) of its row are done
+      // NS steps (dx, chunk) of three groups (dy).  Eight row slots: step st
+      // holds its input row ir in slot kSlot[st % 4][ir]; a slot is refilled as
+      // soon as the kernel rows (dy) of its row are done
       static_assert(RW == 4, "row slot table for 4 output rows per wave");
-      constexpr int kSlot[3][6] = {{0, 1, 2, 3, 4, 5}, {6, 7, 0, 1, 2, 3}, {4, 5, 6, 7, 0, 1}};
-      u32x4_t rh[8], rl[8], afc[NJW], alc[NJW], afn[NJW], aln[NJW];
-      auto load_row = [&](int dx, int ir) {
+      constexpr int NS = 3 * CPH;
+      constexpr int kSlot[4][6] = {
+          {0, 1, 2, 3, 4, 5}, {6, 7, 0, 1, 2, 3}, {4, 5, 6, 7, 0, 1}, {2, 3, 4, 5, 6, 7}};
+      u32x4_t rh[8], rl[SPLIT ? 8 : 1], afc[NJW], alc[NJW], afn[NJW], aln[NJW];
+      auto load_row = [&](int st, int ir) {
+        const int dx = st / CPH, cl = st % CPH;
         const int pix = (wv * RW + ir) * HW_ + c16 + dx;
-        const char* b = lin + pix * C::PIXB + c * 64 + g * 16;
-        rh[kSlot[dx][ir]] = *reinterpret_cast<const u32x4_t*>(b);
-        rl[kSlot[dx][ir]] = *reinterpret_cast<const u32x4_t*>(b + C::LO_OFF);
+        const char* b = lin + pix * C::PIXB + c * HB + cl * 64 + g * 16;
+        rh[kSlot[st % 4][ir]] = *reinterpret_cast<const u32x4_t*>(b);
+        if constexpr (SPLIT) rl[kSlot[st % 4][ir]] = *reinterpret_cast<const u32x4_t*>(b + C::LO_OFF);
       };
-      auto load_w = [&](u32x4_t* hi, u32x4_t* lo, int dx, int dy) {
-        const int ch = (dy * 3 + dx) * C::CPT + c;
+      auto load_w = [&](u32x4_t* hi, u32x4_t* lo, int st, int dy) {
+        const int dx = st / CPH, cl = st % CPH;
+        const int ch = (dy * 3 + dx) * C::CPT + c * CPH + cl;
 #pragma unroll
         for (int j = 0; j < NJW; ++j) {
           hi[j] = lw[(ch * NJW + j) * 64 + lane];
-          lo[j] = lwl[(ch * NJW + j) * 64 + lane];
+          if constexpr (SPLIT) lo[j] = lwl[(ch * NJW + j) * 64 + lane];
         }
       };
 #pragma unroll
       for (int ir = 0; ir < NR; ++ir) load_row(0, ir);
       load_w(afc, alc, 0, 0);
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
+      for (int st = 0; st < NS; ++st) {
+        const int sl = st % 4;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
           // reads for later groups: rows into slots freed by earlier groups
           // (this step's rows 4 and 5 and the next step's rows 0 and 1 in group
           // 0, the next step's rows 2 and 3 in groups 1 and 2), the next
           // group's weight fragments
-          if (dy == 0 && dx > 0) {
-            load_row(dx, 4);
-            load_row(dx, 5);
+          if (dy == 0 && st > 0) {
+            load_row(st, 4);
+            load_row(st, 5);
           }
-          if (dx < 2) {
+          if (st + 1 < NS) {
             if (dy == 0) {
-              load_row(dx + 1, 0);
-              load_row(dx + 1, 1);
+              load_row(st + 1, 0);
+              load_row(st + 1, 1);
             } else {
-              load_row(dx + 1, dy + 1);
+              load_row(st + 1, dy + 1);
             }
           }
           if (dy < 2)
-            load_w(afn, aln, dx, dy + 1);
-          else if (dx < 2)
-            load_w(afn, aln, dx + 1, 0);
+            load_w(afn, aln, st, dy + 1);
+          else if (st + 1 < NS)
+            load_w(afn, aln, st + 1, 0);
+          if constexpr (SPLIT) {
+            // small terms first (lo*hi, hi*lo, then hi*hi), each term over all
+            // accumulators before the next
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rl[kSlot[sl][r + dy]]);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+              for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], alc[j], rh[kSlot[sl][r + dy]]);
+          }
 #pragma unroll
           for (int r = 0; r < RW; ++r)
 #pragma unroll
-            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rl[kSlot[dx][r + dy]]);
-#pragma unroll
-          for (int r = 0; r < RW; ++r)
-#pragma unroll
-            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], alc[j], rh[kSlot[dx][r + dy]]);
-#pragma unroll
-          for (int r = 0; r < RW; ++r)
-#pragma unroll
-            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rh[kSlot[dx][r + dy]]);
-          side(dx * 3 + dy);
+            for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rh[kSlot[sl][r + dy]]);
+          side(st * 3 + dy);
           // spread this group's LDS reads and epilogue work between its MFMAs
+          // (split: 3 products per term; float32: 4 MFMAs per 16-channel chunk)
+          constexpr int NM = (SPLIT ? 3 : 4) * RW * NJW;
 #pragma unroll
-          for (int i = 0; i < 3 * RW * NJW; ++i) {
+          for (int i = 0; i < NM; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
             if (i < 8) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
             __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
@@ -352,7 +376,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
 #pragma unroll
           for (int j = 0; j < NJW; ++j) {
             afc[j] = afn[j];
-            alc[j] = aln[j];
+            if constexpr (SPLIT) alc[j] = aln[j];
           }
         }
       }
@@ -403,20 +427,20 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_split64_kernel(ConvArgs a
 }
 
 // the halo loads address one image through 32-bit byte offsets
-inline bool split64_fits(const ConvArgs& a) {
+inline bool halves_fits(const ConvArgs& a) {
   // an offset pushed out of range (kDropOffset plus at most one image) must
   // stay above the image and below 2^32, one pushed below zero stay negative
   return static_cast<long long>(a.H) * a.W * 256 <= (1LL << 30) && a.W >= 16;
 }
 
-template <int CO, int EPI>
-int launch_split64(const ConvArgs& a, hipStream_t s) {
-  using C = Cfg<PREC_SPLIT, 64, CO, P_NONE>;
+template <int PREC, int CO, int EPI>
+int launch_halves(const ConvArgs& a, hipStream_t s) {
+  using C = Cfg<PREC, 64, CO, P_NONE>;
   constexpr int LDS = C::LDS + 16 * 2 * 4;  // + this workgroup's biases
   static_assert(LDS <= 160 * 1024, "LDS budget");
   static bool attr_set = false;
   static int max_blocks = 0;
-  auto kern = conv_split64_kernel<CO, EPI>;
+  auto kern = conv_halves_kernel<PREC, CO, EPI>;
   constexpr int THREADS = kS64Threads;
   if (!attr_set) {
     IDQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -425,7 +449,7 @@ int launch_split64(const ConvArgs& a, hipStream_t s) {
     IDQ_HIP(hipGetDevice(&dev));
     IDQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     IDQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, THREADS, LDS));
-    if (occ < 1) return fail(IDQ_E_UNSUPPORTED, "split conv does not fit on a compute unit");
+    if (occ < 1) return fail(IDQ_E_UNSUPPORTED, "channel-half conv does not fit on a compute unit");
     max_blocks = ncu * occ;
     attr_set = true;
   }
