@@ -51,8 +51,8 @@ TRAFFIC = {
                     "sha256": "50e5dc950ca482dd7740b759244d83aeccdc69f651b5e18f27c4df722d1bea14",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
-    "conv64_bf16x3": {"bytes_per_px": 673.35,
-                      "sha256": "175c754aeec55a92e4083d33a99d01b9dae80154abe825815029b0d0f4a09140",
+    "conv64_bf16x3": {"bytes_per_px": 673.37,
+                      "sha256": "11ce8c89d1a7db18052586178b48af8a8831e70ee07bfefc5bd1dd709b5c278f",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},
@@ -486,7 +486,7 @@ def main():
                             if sources_sha256(tr["sources"]) == tr["sha256"] else None),
                 "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": per_px * px / launches,
-                "kernel": ("conv_split64_kernel<64>" if split
+                "kernel": ("conv_halves_kernel<bf16x3, 64>" if split
                            else "conv_mfma_kernel<bf16, 64, 64>"),
                 "launches": launches, "sampled_every": args.sample_every,
                 "matrix_core_products_per_flop": 3 if split else 1,
