@@ -295,8 +295,14 @@ def paper_workloads(torch, poll):
         losses = [tr.epoch(Y, Xs, **kw) for _ in range(2)]
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / 2
+        # conv flops of the epoch's forward solves alone (K updates x one
+        # regularizer gradient per pair: forward and transposed passes of the
+        # 3->64->64->64->64->3 net), a lower bound on the epoch's flops
+        fl = 100 * 2 * (2 * 9 * 3 * 64 * 2 + 3 * FLOP_PER_PX_64) * 16 * 128 * 128
         tr_out[mode] = {"s_per_epoch": dt, "pairs_per_s": 16 / dt, "adjoint_iters": adj,
-                        "loss": losses}
+                        "loss": losses, "forward_conv_flops": fl,
+                        "achieved_TFLOPs": fl / dt / 1e12,
+                        "frac_of_fp32_matrix_peak": fl / dt / F32_PEAK}
         tr.close()
     out["training_epoch_16x3x128_f32"] = tr_out
 
@@ -311,8 +317,16 @@ def paper_workloads(torch, poll):
         ws.train_step(yb, tb, 1e-4, prec="bf16", want_loss=False)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / 10
+    # flops of one step: the forward pass, the backward pass and the weight
+    # gradient, each ~ the network's conv flops (full resolution: 3->32, 32->32,
+    # 96->32, 32->32, 32->3; half resolution: 32->64 and 3 x 64->64)
+    fwd_px = 2 * 9 * (3 * 32 + 32 * 32 + 96 * 32 + 32 * 32 + 32 * 3) + \
+        2 * 9 * (32 * 64 + 3 * 64 * 64) // 4
+    fl = 3 * fwd_px * 16 * 128 * 128
     out["warmstart_train_step_16x3x128_bf16"] = {"ms_per_step": 1e3 * dt, "pairs_per_s": 16 / dt,
-                                                 "params": ws.num_params}
+                                                 "params": ws.num_params, "conv_flops": fl,
+                                                 "achieved_TFLOPs": fl / dt / 1e12,
+                                                 "frac_of_bf16_peak": fl / dt / BF16_PEAK}
     return out
 
 
