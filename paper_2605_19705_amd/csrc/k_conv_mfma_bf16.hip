@@ -1,5 +1,6 @@
 // bf16 instantiations of the implicit-GEMM conv (kernel in k_conv_mfma.h).
 #include "k_conv_mfma.h"
+#include "k_conv_split64.h"
 
 namespace idq {
 namespace mfma {
@@ -8,6 +9,16 @@ namespace {
 
 template <int CI, int CO, int PRO>
 int by_epi(const ConvArgs& a, hipStream_t s) {
+  if constexpr (CI == 64 && (CO == 64 || CO == 32) && PRO == P_NONE) {
+    if (halves_fits(a)) {
+      switch (a.epi) {
+        case E_ACT: return launch_halves<PREC_BF16, CO, E_ACT>(a, s);
+        case E_DELTA: return launch_halves<PREC_BF16, CO, E_DELTA>(a, s);
+        case E_RAW: return launch_halves<PREC_BF16, CO, E_RAW>(a, s);
+        default: break;
+      }
+    }
+  }
   switch (a.epi) {
     case E_ACT: return launch_shape<PREC_BF16, CI, CO, PRO, E_ACT>(a, s);
     case E_DELTA: return launch_shape<PREC_BF16, CI, CO, PRO, E_DELTA>(a, s);

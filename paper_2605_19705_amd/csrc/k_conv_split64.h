@@ -1,15 +1,16 @@
-// Split-bf16 and float32 3x3 convolutions from 64 input channels (to 32 or 64
-// outputs), software-pipelined over the two halves of the input channels,
-// with the halo traffic on waves of its own.
+// 3x3 convolutions from 64 input channels (to 32 or 64 outputs) in split-bf16,
+// bf16 or float32 arithmetic, software-pipelined over the two halves of the
+// input channels, with the halo traffic on waves of its own.
 //
 // Same arithmetic as conv_mfma_kernel (k_conv_mfma.h).  Split: float
 // activations and float weights each taken as a bf16 hi part plus the bf16
 // rounding of the remainder, acc += W_lo x_hi + W_hi x_lo + W_hi x_hi on
-// v_mfma_f32_16x16x32_bf16.  Float32: v_mfma_f32_16x16x4f32 on float4 slices of
-// 16-channel K chunks.  32 output channels per workgroup (two workgroups per
-// tile for 64 outputs, on one XCD), the 18 x 18 halo tile and this workgroup's
-// weight fragments (split: hi and lo) in LDS (161,856 bytes: one workgroup per
-// compute unit).
+// v_mfma_f32_16x16x32_bf16.  Bf16: bf16 activations, one product.  Float32:
+// v_mfma_f32_16x16x4f32 on float4 slices of 16-channel K chunks.  Split and
+// float32 take 32 output channels per workgroup (two workgroups per tile for
+// 64 outputs, on one XCD) so that the weight fragments (split: hi and lo) fit
+// in LDS beside the 18 x 18 halo tile (161,856 bytes: one workgroup per
+// compute unit); bf16 takes all 64.
 //
 // What differs is the schedule.  The K loop runs channel half 0 (K chunks of
 // input channels 0..31, all 9 taps) and then channel half 1.  Each half reads
@@ -18,17 +19,17 @@
 // while half 1 is, half 0 of the next tile does: the LDS footprint stays that
 // of one tile.  The workgroup's 8 waves split the work: waves 0..3 (one per
 // SIMD, 4 output rows each) run the K loop and the epilogue; waves 4..7 load
-// the halo from HBM one half ahead, split it into hi and lo parts and write it
-// to LDS.  A vector memory instruction in a wave that feeds the matrix core
-// holds up its MFMA stream; on the helper waves it only occupies the SIMD's
-// issue slots the MFMA wave leaves free.  The epilogue (SoftPlus or sigma',
-// stores) of a tile follows its K loop.  Per matrix wave and (dx, chunk)
-// step the six input rows are read once for the three kernel rows (dy) that
-// use them, a third of them per group during the previous step; weight
-// fragment reads are issued one matrix-core group ahead; scheduling-group
-// hints spread the reads between the MFMAs.  Both kinds of wave walk the same
-// tiles and meet at the same two barriers per tile, in loops of their own (so
-// that their registers are not live at once).
+// the halo from HBM one half ahead, split it into hi and lo parts (split
+// arithmetic) and write it to LDS.  A vector memory instruction in a wave that
+// feeds the matrix core holds up its MFMA stream; on the helper waves it only
+// occupies the SIMD's issue slots the MFMA wave leaves free.  The epilogue
+// (SoftPlus or sigma', stores) of a tile follows its K loop.  Per matrix wave
+// and (dx, chunk) step the six input rows are read once for the three kernel
+// rows (dy) that use them, a third of them per group during the previous
+// step; weight fragment reads are issued one matrix-core group ahead;
+// scheduling-group hints spread the reads between the MFMAs.  Both kinds of
+// wave walk the same tiles and meet at the same two barriers per tile, in
+// loops of their own (so that their registers are not live at once).
 #pragma once
 
 #include "k_conv_mfma.h"
@@ -42,20 +43,22 @@ template <int PREC, int CO, int EPI>
 __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a, int ntx,
                                                                      int nty, int ntiles) {
   using C = Cfg<PREC, 64, CO, P_NONE>;
-  constexpr bool SPLIT = PREC == PREC_SPLIT;
-  static_assert(SPLIT || PREC == PREC_F32, "split-bf16 or float32 arithmetic");
-  static_assert(C::NJW == 2 && TW == 16 && C::WLDS && (!SPLIT || C::WLO_LDS) &&
-                    (SPLIT ? (C::CPT == 2 && C::LO_OFF == 128) : C::CPT == 4),
+  constexpr bool SPLIT = PREC == PREC_SPLIT, BF = PREC == PREC_BF16;
+  static_assert(SPLIT || BF || PREC == PREC_F32, "split-bf16, bf16 or float32 arithmetic");
+  static_assert((C::NJW == 2 || C::NJW == 4) && TW == 16 && C::WLDS && (!SPLIT || C::WLO_LDS) &&
+                    (SPLIT ? (C::CPT == 2 && C::LO_OFF == 128) : C::CPT == (BF ? 2 : 4)),
                 "shape of the channel-half pipeline");
-  static_assert(EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW, "NHWC float outputs");
-  constexpr int NT_ = kS64Threads / 2, RW = TH / (NT_ / 64), NJW = 2, NR = RW + 2;
-  // K chunks of one half per tap (split: 32 channels; float32: 2 x 16), and
-  // the LDS bytes of a channel quad and of a half within a halo pixel
+  static_assert(EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW, "NHWC activation outputs");
+  constexpr int NT_ = kS64Threads / 2, RW = TH / (NT_ / 64), NJW = C::NJW, NR = RW + 2;
+  // K chunks of one half per tap (split and bf16: 32 channels; float32: 2 x
+  // 16), the LDS bytes of a channel quad (float32 in HBM) and of a half within
+  // a halo pixel, and the bytes of an activation in HBM
   constexpr int CPH = C::CPT / 2;
-  constexpr int QB = SPLIT ? 8 : 16, HB = SPLIT ? 64 : 128;
+  constexpr int QB = SPLIT ? 8 : 16, HB = SPLIT || BF ? 64 : 128, EB = BF ? 2 : 4;
 
-  // 16-byte items (4 channels of one pixel) of one channel half, per thread
-  constexpr int HITEMS = NPIX * 8;
+  // 16-byte items of one channel half (4 float or 8 bf16 channels of one
+  // pixel), per thread
+  constexpr int HITEMS = NPIX * (BF ? 4 : 8);
   constexpr int NHI = (HITEMS + NT_ - 1) / NT_;
   static_assert(RW % 2 == 0, "sigma(h) is read in two groups");
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -104,8 +107,8 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
   // above or below it, or an offset pushed past it for a column outside it)
   // reads zero.  Branch-free, so that it can be scheduled among the MFMAs:
   // past the last tile the resource covers zero bytes.
-  static_assert(NT_ == 256 && TW == 16 && NHI == 11, "halo item layout");
-  const unsigned img_bytes = static_cast<unsigned>(a.H * a.W) * 256u;
+  static_assert(NT_ == 256 && TW == 16 && NHI == (BF ? 6 : 11), "halo item layout");
+  const unsigned img_bytes = static_cast<unsigned>(a.H * a.W) * (64u * EB);
   const int htid = tid & (NT_ - 1);  // thread index among the halo waves
   // inner column of this thread's items: 8-lane groups take columns in the
   // order 0, 4, 1, 5, 2, 6, 3, 7, 8, 12, ..., so that the two groups of 16
@@ -134,12 +137,20 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
         real ? img_bytes : 0u);
     // byte offset of halo pixel (0, 0) of this tile and half (negative on the
     // top row of images: those rows read zero)
-    const int org = ((ty0 - 1) * a.W + tx0 - 1) * 256 + h * 128;
+    const int org = ((ty0 - 1) * a.W + tx0 - 1) * 256 + h * 128;  // float32 layouts
     const int base_i = tx0 - 1 + col_i < a.W ? thr_int : static_cast<int>(kDropOffset);
 #pragma unroll
     for (int k = k0; k < k1; ++k) {
       int off;
-      if (k < 9) {
+      if constexpr (BF) {
+        // bf16: item it = htid + 256 k is pixel it / 4, channels 32 h + 8 (it % 4) .. + 7
+        const int it = htid + k * NT_, p = it >> 2, q = it & 3;
+        const int ly = p / HW_, lx = p - (p / HW_) * HW_;
+        const int gy = ty0 - 1 + ly, gx = tx0 - 1 + lx;
+        const bool in = it < HITEMS && static_cast<unsigned>(gy) < static_cast<unsigned>(a.H) &&
+                        static_cast<unsigned>(gx) < static_cast<unsigned>(a.W);
+        off = in ? (gy * a.W + gx) * 128 + h * 64 + q * 16 : static_cast<int>(kDropOffset);
+      } else if (k < 9) {
         off = base_i + (org + k * 2 * a.W * 256);
       } else {
         const int m = k - 9;
@@ -153,6 +164,12 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
   // item k into the half's LDS bytes: split, the hi parts and the
   // bf16-rounded remainders; float32, the values
   auto store_item = [&](const u32x4_t (&buf)[NHI], int k, int h) {
+    if constexpr (BF) {
+      const int it = htid + k * NT_;
+      if ((k + 1) * NT_ <= HITEMS || it < HITEMS)
+        *reinterpret_cast<u32x4_t*>(lin + (it >> 2) * C::PIXB + h * HB + (it & 3) * 16) = buf[k];
+      return;
+    }
     // items 0..9 exist for every thread, item 10 for the first 32
     if (k < 10 || htid < HITEMS - 10 * NT_) {
       const u32x4_t val = buf[k];
@@ -202,7 +219,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
       }
     }
   }
-  // this workgroup's 32 biases, after the weights (read by the epilogue)
+  // this workgroup's 16 NJW biases, after the weights (read by the epilogue)
   float* lbias = reinterpret_cast<float*>(smem + C::LDS);
   if (tid < 16 * NJW) {
     const float* bias = static_cast<const float*>(a.bias);
@@ -235,12 +252,16 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
     return;
   }
 
-  // the tile's sigma(h) operand (E_DELTA)
-  u32x4_t e0v[RW][NJW];
+  // the tile's sigma(h) operand (E_DELTA): 4 channels per piece, as floats or
+  // packed bf16
+  constexpr int EW = BF ? 2 : 4;
+  unsigned e0v[RW][NJW][EW];
 #pragma unroll
   for (int r = 0; r < RW; ++r)
 #pragma unroll
-    for (int j = 0; j < NJW; ++j) e0v[r][j] = u32x4_t{0u, 0u, 0u, 0u};
+    for (int j = 0; j < NJW; ++j)
+#pragma unroll
+      for (int i = 0; i < EW; ++i) e0v[r][j][i] = 0u;
   // the output resource over the tile's rows, and the lane part of a piece's
   // byte offset in them (past the image's right edge: pushed beyond the
   // resource)
@@ -258,21 +279,34 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
       // both forms computed and selected (no branch among the MFMAs)
       if constexpr (EPI == E_ACT) {
         const float hv = x + (i == 0 ? bias4.x : i == 1 ? bias4.y : i == 2 ? bias4.z : bias4.w);
-        const float y = softplus_hw(hv);
+        const float y = BF ? softplus_fast(hv) : softplus_hw(hv);
         v[i] = sp ? y : hv;
       } else if constexpr (EPI == E_DELTA) {
-        const float d = dsp_from_a_hw(u2f(e0v[r][jj][i]));
+        const float av = BF ? u2f((e0v[r][jj][i >> 1] << ((i & 1) ? 0 : 16)) & 0xffff0000u)
+                            : u2f(e0v[r][jj][i]);
+        const float d = BF ? dsp_from_a_fast(av) : dsp_from_a_hw(av);
         v[i] = (sp ? d : 1.f) * x;
       } else {
         v[i] = x;
       }
     }
     // rows past the image's bottom edge fall outside the resource
-    const int off = plane + (ly * a.W * CO * 4 + jj * 64);
-    const u32x4_v pk = {f2u(v[0]), f2u(v[1]), f2u(v[2]), f2u(v[3])};
-    __builtin_amdgcn_raw_buffer_store_b128(pk, prs, off, 0, 0);
+    const int off = plane + (ly * a.W * CO * EB + jj * 16 * EB);
+    if constexpr (BF) {
+      const u32x2_v pk = {pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])};
+      __builtin_amdgcn_raw_buffer_store_b64(pk, prs, off, 0, 0);
+    } else {
+      const u32x4_v pk = {f2u(v[0]), f2u(v[1]), f2u(v[2]), f2u(v[3])};
+      __builtin_amdgcn_raw_buffer_store_b128(pk, prs, off, 0, 0);
+    }
   };
 
+  // LDS bases of this lane's row and weight reads: every read is one of them
+  // plus an immediate offset below 64 KB (left to itself the compiler keeps an
+  // address register per row and weight block, some 90 VGPRs)
+  const char* rbase = lin + ((wvu * RW * HW_ + c16) * C::PIXB + g * 16);
+  const u32x4_t* whb = lw + lane;
+  const u32x4_t* wlb = lwl + lane;
   while (t < ntiles) {
     const int tn = next_open(t);
     const int ni = t / tiles_per_img;
@@ -301,8 +335,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
       u32x4_t rh[8], rl[SPLIT ? 8 : 1], afc[NJW], alc[NJW], afn[NJW], aln[NJW];
       auto load_row = [&](int st, int ir) {
         const int dx = st / CPH, cl = st % CPH;
-        const int pix = (wv * RW + ir) * HW_ + c16 + dx;
-        const char* b = lin + pix * C::PIXB + c * HB + cl * 64 + g * 16;
+        const char* b = rbase + ((ir * HW_ + dx) * C::PIXB + c * HB + cl * 64);
         rh[kSlot[st % 4][ir]] = *reinterpret_cast<const u32x4_t*>(b);
         if constexpr (SPLIT) rl[kSlot[st % 4][ir]] = *reinterpret_cast<const u32x4_t*>(b + C::LO_OFF);
       };
@@ -311,8 +344,8 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
         const int ch = (dy * 3 + dx) * C::CPT + c * CPH + cl;
 #pragma unroll
         for (int j = 0; j < NJW; ++j) {
-          hi[j] = lw[(ch * NJW + j) * 64 + lane];
-          if constexpr (SPLIT) lo[j] = lwl[(ch * NJW + j) * 64 + lane];
+          hi[j] = whb[(ch * NJW + j) * 64];
+          if constexpr (SPLIT) lo[j] = wlb[(ch * NJW + j) * 64];
         }
       };
 #pragma unroll
@@ -360,9 +393,9 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
 #pragma unroll
             for (int j = 0; j < NJW; ++j) mma<C>(acc[r][j], afc[j], rh[kSlot[sl][r + dy]]);
           side(st * 3 + dy);
-          // spread this group's LDS reads and epilogue work between its MFMAs
+          // spread this group's LDS reads and side work between its MFMAs
           // (split: 3 products per term; float32: 4 MFMAs per 16-channel chunk)
-          constexpr int NM = (SPLIT ? 3 : 4) * RW * NJW;
+          constexpr int NM = (SPLIT ? 3 : BF ? 1 : 4) * RW * NJW;
 #pragma unroll
           for (int i = 0; i < NM; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
@@ -396,27 +429,34 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
         const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
         const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
         const __amdgpu_buffer_rsrc_t ers =
-            out_rsrc(const_cast<char*>(static_cast<const char*>(a.e0)) + row0 * 4,
-                     static_cast<unsigned>(rows) * a.W * CO * 4);
-        const int lane_off = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * 4
+            out_rsrc(const_cast<char*>(static_cast<const char*>(a.e0)) + row0 * EB,
+                     static_cast<unsigned>(rows) * a.W * CO * EB);
+        const int lane_off = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * EB
                                              : static_cast<int>(kDropOffset);
 #pragma unroll
         for (int r = (grp - 5) * RW / 2; r < (grp - 4) * RW / 2; ++r)
 #pragma unroll
           for (int jj = 0; jj < NJW; ++jj) {
-            const int off = lane_off + ((wvu * RW + r) * a.W * CO * 4 + jj * 64);
-            const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(ers, off, 0, 0);
-            e0v[r][jj] = u32x4_t{v[0], v[1], v[2], v[3]};
+            const int off = lane_off + ((wvu * RW + r) * a.W * CO * EB + jj * 16 * EB);
+            if constexpr (BF) {
+              const u32x2_v v = __builtin_amdgcn_raw_buffer_load_b64(ers, off, 0, 0);
+              e0v[r][jj][0] = v[0];
+              e0v[r][jj][1] = v[1];
+            } else {
+              const u32x4_v v = __builtin_amdgcn_raw_buffer_load_b128(ers, off, 0, 0);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) e0v[r][jj][i] = v[i];
+            }
           }
       }
     });
     __syncthreads();  // the next tile's half 0 is in LDS, half 1 has been read
-    plane = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * 4
+    plane = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * EB
                             : static_cast<int>(kDropOffset);
     {
       const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
       const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
-      prs = out_rsrc(static_cast<char*>(a.out0) + row0 * 4, static_cast<unsigned>(rows) * a.W * CO * 4);
+      prs = out_rsrc(static_cast<char*>(a.out0) + row0 * EB, static_cast<unsigned>(rows) * a.W * CO * EB);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r)
@@ -436,7 +476,7 @@ inline bool halves_fits(const ConvArgs& a) {
 template <int PREC, int CO, int EPI>
 int launch_halves(const ConvArgs& a, hipStream_t s) {
   using C = Cfg<PREC, 64, CO, P_NONE>;
-  constexpr int LDS = C::LDS + 16 * 2 * 4;  // + this workgroup's biases
+  constexpr int LDS = C::LDS + 16 * C::NJW * 4;  // + this workgroup's biases
   static_assert(LDS <= 160 * 1024, "LDS budget");
   static bool attr_set = false;
   static int max_blocks = 0;
