@@ -47,12 +47,13 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # pixels per timed launch.  A figure is valid only while the kernel's device
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
-    "conv64_bf16": {"bytes_per_px": 336.90,
-                    "sha256": "50e5dc950ca482dd7740b759244d83aeccdc69f651b5e18f27c4df722d1bea14",
+    "conv64_bf16": {"bytes_per_px": 336.69,
+                    "sha256": "048644618cc3925438fbb127e639d52be979282625cabff47b7f3143ec8c7bfd",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
+                                "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
-    "conv64_bf16x3": {"bytes_per_px": 673.37,
-                      "sha256": "11ce8c89d1a7db18052586178b48af8a8831e70ee07bfefc5bd1dd709b5c278f",
+    "conv64_bf16x3": {"bytes_per_px": 673.39,
+                      "sha256": "03cf93cf39b4d9dfd6074072f8f61c27dee0ea2e599e7b34a05b366c9e6d88db",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},
@@ -501,7 +502,7 @@ def main():
                 "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": per_px * px / launches,
                 "kernel": ("conv_halves_kernel<bf16x3, 64>" if split
-                           else "conv_mfma_kernel<bf16, 64, 64>"),
+                           else "conv_halves_kernel<bf16, 64>"),
                 "launches": launches, "sampled_every": args.sample_every,
                 "matrix_core_products_per_flop": 3 if split else 1,
                 "frac_of_product_ceiling": achieved / (peak / (3.0 if split else 1.0)),
