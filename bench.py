@@ -48,12 +48,12 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
     "conv64_bf16": {"bytes_per_px": 336.69,
-                    "sha256": "048644618cc3925438fbb127e639d52be979282625cabff47b7f3143ec8c7bfd",
+                    "sha256": "7cd3cdac4a057805333e5fca3b5c765a21351b621993b22759237fa1cfc6156f",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
     "conv64_bf16x3": {"bytes_per_px": 673.39,
-                      "sha256": "03cf93cf39b4d9dfd6074072f8f61c27dee0ea2e599e7b34a05b366c9e6d88db",
+                      "sha256": "0318c143a852bfc92a9df738e87847797b34fb7a1af163c98fa1f32662d11804",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},

@@ -97,7 +97,9 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
     return tt;
   };
 
-  // Items of a half (16 bytes: 4 channels of one halo pixel).  Items 0..8 of
+  // Items of a half, float activations (16 bytes: 4 channels of one halo
+  // pixel; bf16 activations: 8 channels, item i of the tile is quarter i % 4 of
+  // the half of pixel i / 4, copied as loaded).  Items 0..8 of
   // a thread walk the 16 inner columns two rows at a time: row 2k + tid / 128,
   // column 1 + (tid / 8) % 16, channel quad tid % 8, so that one item's offset
   // is the thread's offset plus a uniform step.  Items 9 and 10 cover the two
@@ -135,9 +137,9 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
     const __amdgpu_buffer_rsrc_t rs = out_rsrc(
         const_cast<char*>(static_cast<const char*>(a.in0)) + static_cast<size_t>(ni) * img_bytes,
         real ? img_bytes : 0u);
-    // byte offset of halo pixel (0, 0) of this tile and half (negative on the
-    // top row of images: those rows read zero)
-    const int org = ((ty0 - 1) * a.W + tx0 - 1) * 256 + h * 128;  // float32 layouts
+    // byte offset of halo pixel (0, 0) of this tile and half, float
+    // activations (negative on the top row of images: those rows read zero)
+    const int org = ((ty0 - 1) * a.W + tx0 - 1) * 256 + h * 128;
     const int base_i = tx0 - 1 + col_i < a.W ? thr_int : static_cast<int>(kDropOffset);
 #pragma unroll
     for (int k = k0; k < k1; ++k) {
