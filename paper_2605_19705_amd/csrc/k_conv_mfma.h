@@ -886,7 +886,7 @@ int launch_shape(const ConvArgs& a, hipStream_t s) {
 #define IDQ_MFMA_THIN(X) X(16, 1) X(64, 3) X(32, 3)
 // split (hi/lo bf16) instantiations: the channel counts that are whole K chunks
 // (image-facing outputs run in float32 on the vector ALUs, k_conv_thin.hip)
-#define IDQ_MFMA_SPLIT(X) X(64, 64) X(32, 32) X(32, 64) X(64, 32)
+#define IDQ_MFMA_SPLIT(X) X(64, 64) X(32, 32) X(32, 64) X(64, 32) X(64, 3)
 
 }  // namespace mfma
 }  // namespace idq

@@ -45,10 +45,16 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
   using C = Cfg<PREC, 64, CO, P_NONE>;
   constexpr bool SPLIT = PREC == PREC_SPLIT, BF = PREC == PREC_BF16;
   static_assert(SPLIT || BF || PREC == PREC_F32, "split-bf16, bf16 or float32 arithmetic");
-  static_assert((C::NJW == 2 || C::NJW == 4) && TW == 16 && C::WLDS && (!SPLIT || C::WLO_LDS) &&
+  // THIN: an image-facing output (CO <= 4 NCHW state channels, one block of 16
+  // matrix rows of which CO are used)
+  constexpr bool THIN = CO <= 4;
+  static_assert((THIN ? C::NJW == 1 : (C::NJW == 2 || C::NJW == 4)) && TW == 16 && C::WLDS &&
+                    (!SPLIT || C::WLO_LDS) &&
                     (SPLIT ? (C::CPT == 2 && C::LO_OFF == 128) : C::CPT == (BF ? 2 : 4)),
                 "shape of the channel-half pipeline");
-  static_assert(EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW, "NHWC activation outputs");
+  static_assert(THIN ? (EPI == E_RES || EPI == E_SUB)
+                     : (EPI == E_ACT || EPI == E_DELTA || EPI == E_RAW),
+                "NHWC activation outputs, or NCHW state outputs for CO <= 4");
   constexpr int NT_ = kS64Threads / 2, RW = TH / (NT_ / 64), NJW = C::NJW, NR = RW + 2;
   // K chunks of one half per tap (split and bf16: 32 channels; float32: 2 x
   // 16), the LDS bytes of a channel quad (float32 in HBM) and of a half within
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
   }
 
   // the tile's sigma(h) operand (E_DELTA): 4 channels per piece, as floats or
-  // packed bf16
+  // packed bf16; for THIN outputs the state operand e0 of the CO channels
   constexpr int EW = BF ? 2 : 4;
   unsigned e0v[RW][NJW][EW];
 #pragma unroll
@@ -270,8 +276,24 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
   __amdgpu_buffer_rsrc_t prs = out_rsrc(a.out0, 0u);
   const int wvu = __builtin_amdgcn_readfirstlane(wv);
   int plane = static_cast<int>(kDropOffset);
+  // THIN: rows of the tile inside the image
+  int rows_in = 0;
   auto piece = [&](int r, int jj, const f32x4_t& accv) {
     const int ly = wvu * RW + r;
+    if constexpr (THIN) {
+      // lanes 0..15 hold output channels 0..3 of pixel c16 (channels >= CO are
+      // padding); NCHW planes of the tile's image, rows past its bottom dropped
+      const bool ok = ly < rows_in && plane != static_cast<int>(kDropOffset);
+#pragma unroll
+      for (int i = 0; i < CO; ++i) {
+        const float x = accv[i];
+        const float e = u2f(e0v[r][0][i]);
+        const float v = EPI == E_RES ? e - (x + lbias[i]) : e - x;
+        const int off = ok ? plane + (ly * a.W + i * a.H * a.W) * 4 : static_cast<int>(kDropOffset);
+        __builtin_amdgcn_raw_buffer_store_b32(f2u(v), prs, off, 0, 0);
+      }
+      return;
+    }
     float v[4];
     float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (EPI == E_ACT) bias4 = *reinterpret_cast<const float4*>(lbias + 16 * jj + 4 * g);
@@ -425,6 +447,27 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
     half(0, [&](int) {});
     __syncthreads();  // half 1 is in LDS, half 0 has been read
     half(1, [&](int grp) {
+      if (THIN && (grp == 5 || grp == 6)) {
+        // this tile's e0 (z for E_RES, r for E_SUB), half of the rows per group
+        const __amdgpu_buffer_rsrc_t ers =
+            out_rsrc(const_cast<char*>(static_cast<const char*>(a.e0)) +
+                         static_cast<size_t>(ni) * CO * a.H * a.W * 4,
+                     static_cast<unsigned>(CO * a.H * a.W * 4));
+        const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
+        const int lane_off = g == 0 && tx0 + c16 < a.W ? (ty0 * a.W + tx0 + c16) * 4
+                                                       : static_cast<int>(kDropOffset);
+#pragma unroll
+        for (int r = (grp - 5) * RW / 2; r < (grp - 4) * RW / 2; ++r) {
+          const int ly = wvu * RW + r;
+          const bool ok = ly < rows && lane_off != static_cast<int>(kDropOffset);
+#pragma unroll
+          for (int i = 0; i < CO; ++i) {
+            const int off = ok ? lane_off + (ly * a.W + i * a.H * a.W) * 4
+                               : static_cast<int>(kDropOffset);
+            e0v[r][0][i] = __builtin_amdgcn_raw_buffer_load_b32(ers, off, 0, 0);
+          }
+        }
+      }
       if (EPI == E_DELTA && (grp == 5 || grp == 6)) {
         // this tile's sigma(h) (half of it per group), through a resource over
         // its rows: pixels past the image edge read zero
@@ -453,9 +496,17 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
       }
     });
     __syncthreads();  // the next tile's half 0 is in LDS, half 1 has been read
-    plane = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * EB
-                            : static_cast<int>(kDropOffset);
-    {
+    if constexpr (THIN) {
+      // NCHW planes of the tile's image; lane part of the offset of its pixel
+      // in the tile's first row
+      rows_in = a.H - ty0 < TH ? a.H - ty0 : TH;
+      plane = g == 0 && tx0 + c16 < a.W ? (ty0 * a.W + tx0 + c16) * 4
+                                        : static_cast<int>(kDropOffset);
+      prs = out_rsrc(static_cast<char*>(a.out0) + static_cast<size_t>(ni) * CO * a.H * a.W * 4,
+                     static_cast<unsigned>(CO * a.H * a.W * 4));
+    } else {
+      plane = tx0 + c16 < a.W ? ((tx0 + c16) * CO + 16 * jh * NJW + 4 * g) * EB
+                              : static_cast<int>(kDropOffset);
       const int rows = a.H - ty0 < TH ? a.H - ty0 : TH;
       const size_t row0 = (static_cast<size_t>(ni) * a.H + ty0) * a.W * CO;
       prs = out_rsrc(static_cast<char*>(a.out0) + row0 * EB, static_cast<unsigned>(rows) * a.W * CO * EB);
