@@ -48,12 +48,12 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
     "conv64_bf16": {"bytes_per_px": 336.69,
-                    "sha256": "7cd3cdac4a057805333e5fca3b5c765a21351b621993b22759237fa1cfc6156f",
+                    "sha256": "12e2216cc0116cd9e2039be0f31533f9c174c49420ee1bae6bcf7bb91b259f51",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
     "conv64_bf16x3": {"bytes_per_px": 673.39,
-                      "sha256": "0318c143a852bfc92a9df738e87847797b34fb7a1af163c98fa1f32662d11804",
+                      "sha256": "dc5d4c435b8f5d3fa40d72e96b36bce5d3f52c3c623c7d55e051eff8965a8405",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},

@@ -77,7 +77,8 @@ def test_grad_reg_parity(name, c, shape, rng):
     gbf = ctx.grad_reg(to_gpu(x, torch.float32), conv_prec="bf16")
     assert rel_err(to_np(gbf), ref) < 2e-2
     # split bf16 (hi*hi + lo*hi + hi*lo): products good to ~2^-16, float32
-    # tolerance; the 64-channel passes run split, the image-facing ones float32
+    # tolerance; the passes from 64 channels run split (the 3-channel output on
+    # the channel-half kernel from 16 columns, the generic one below), 3->64 float32
     gx3 = ctx.grad_reg(to_gpu(x, torch.float32), conv_prec="bf16x3")
     assert np.max(np.abs(to_np(gx3) - ref)) < 1e-4
     assert rel_err(to_np(gx3), ref) < 1e-4
