@@ -48,12 +48,12 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
     "conv64_bf16": {"bytes_per_px": 336.69,
-                    "sha256": "12e2216cc0116cd9e2039be0f31533f9c174c49420ee1bae6bcf7bb91b259f51",
+                    "sha256": "8add00e330dba3f76cc9e80750609b394be5560dde50486161d1da76ce5da83b",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
     "conv64_bf16x3": {"bytes_per_px": 673.39,
-                      "sha256": "dc5d4c435b8f5d3fa40d72e96b36bce5d3f52c3c623c7d55e051eff8965a8405",
+                      "sha256": "d305023531d5bd5747d7184f8c0bab796dd43a2a540089d40af80273c28406c0",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},

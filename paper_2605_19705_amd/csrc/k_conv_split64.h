@@ -1,6 +1,7 @@
-// 3x3 convolutions from 64 input channels (to 32 or 64 outputs) in split-bf16,
-// bf16 or float32 arithmetic, software-pipelined over the two halves of the
-// input channels, with the halo traffic on waves of its own.
+// 3x3 convolutions from 64 input channels (to 32 or 64 activation channels, or
+// in split-bf16 to 3 NCHW state channels) in split-bf16, bf16 or float32
+// arithmetic, software-pipelined over the two halves of the input channels,
+// with the halo traffic on waves of its own.
 //
 // Same arithmetic as conv_mfma_kernel (k_conv_mfma.h).  Split: float
 // activations and float weights each taken as a bf16 hi part plus the bf16
