@@ -48,12 +48,12 @@ FLOP_PER_PX_64 = 2 * 9 * 64 * 64   # one 64->64 3x3 conv pass
 # code is the one measured (sha256 of its sources), else it is reported as null.
 TRAFFIC = {
     "conv64_bf16": {"bytes_per_px": 336.69,
-                    "sha256": "8add00e330dba3f76cc9e80750609b394be5560dde50486161d1da76ce5da83b",
+                    "sha256": "2f12adc0dacffb85e211299a47045de1c257af3ce9f5872c4043d5a2e57ea122",
                     "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                 "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                 "paper_2605_19705_amd/csrc/k_conv_mfma_bf16.hip")},
     "conv64_bf16x3": {"bytes_per_px": 673.39,
-                      "sha256": "d305023531d5bd5747d7184f8c0bab796dd43a2a540089d40af80273c28406c0",
+                      "sha256": "093520476a45508be24cc7f27c22a9afca5b4ed3e8b8c36f741d801a64289580",
                       "sources": ("paper_2605_19705_amd/csrc/k_conv_mfma.h",
                                   "paper_2605_19705_amd/csrc/k_conv_split64.h",
                                   "paper_2605_19705_amd/csrc/k_conv_mfma_split.hip")},

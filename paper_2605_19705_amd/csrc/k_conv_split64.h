@@ -11,7 +11,8 @@
 // float32 take 32 output channels per workgroup (two workgroups per tile for
 // 64 outputs, on one XCD) so that the weight fragments (split: hi and lo) fit
 // in LDS beside the 18 x 18 halo tile (161,856 bytes: one workgroup per
-// compute unit); bf16 takes all 64.
+// compute unit); bf16 takes all 64, and a 3-channel output one block of 16
+// matrix rows.
 //
 // What differs is the schedule.  The K loop runs channel half 0 (K chunks of
 // input channels 0..31, all 9 taps) and then channel half 1.  Each half reads
@@ -440,11 +441,11 @@ __global__ __launch_bounds__(kS64Threads, 1) void conv_halves_kernel(ConvArgs a,
       }
     };
 
-    // Side work of the matrix waves: this tile's sigma(h) operand, read in
-    // groups 5..6 of half 1 (not held through the rest of it).  The epilogue
-    // follows the K loop: holding a second accumulator set to overlap it with
-    // the next tile's K loop takes more registers than two waves per SIMD have
-    // (and measured no faster where it fitted).
+    // Side work of the matrix waves: this tile's sigma(h) operand (or for a
+    // 3-channel output its e0 state), read in groups 5..6 of half 1 (not held
+    // through the rest of it).  The epilogue follows the K loop: spreading it
+    // over the next tile's half 0, with a second accumulator set, measured no
+    // faster.
     half(0, [&](int) {});
     __syncthreads();  // half 1 is in LDS, half 0 has been read
     half(1, [&](int grp) {
